@@ -1,0 +1,219 @@
+"""Benchmark: FP64 DG volume derivative throughput on one MI355X.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-forms]
+
+One step = one dg_volume call (reference derivatives on the FP64 matrix
+cores, fused geometric-factor combine) over the whole synthetic mesh of the
+headline workload: order 4 (Np = 35), K = 2^20 jittered affine tetrahedra,
+F = 5 fields u ~ N(0,1), element-major FP64, inputs resident in HBM.
+
+Prints one JSON line: GDOF/s (K F Np per second), the HBM roofline of the
+kernel measured with HIP events on the launch stream, the FP64 oracle timed on
+the host cores on a bounded sample, and the split-BF16 form and the adjoint
+measured beside it.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DG volume GDOF/s + % HBM/MFMA roofline; plain FP64 vs chosen form"
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFS = 78.6           # MI355X FP64 (vector and matrix)
+BF16_PEAK_TFS = 2500.0         # MI355X dense BF16 matrix
+KERNEL_SRC = os.path.join(ROOT, "paper_1503_07659_amd", "csrc", "dgvol_kernels.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dg_volume_fwd_f64_order4_K1048576_F5.txt")
+
+
+def fwd_bytes_per_element(F, Np, word=8):
+    """u read once, three output planes written once, nine geometric factors read once."""
+    return word * (4 * F * Np + 9)
+
+
+def fwd_flops_per_element(F, Np):
+    """3 Np x Np products per column (2 flops per multiply-add) plus the 3x3 combine (15 flops/node)."""
+    return F * Np * (6 * Np + 15)
+
+
+def adj_bytes_per_element(F, Np):
+    """u, gout (3 planes) read, gu written; G read and gG written."""
+    return 8 * (F * Np + 3 * F * Np + F * Np) + 144
+
+
+def adj_flops_per_element(F, Np):
+    return F * Np * (12 * Np + 33)
+
+
+def kernel_source_sha():
+    with open(KERNEL_SRC, "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()
+
+
+def recorded_traffic():
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
+    taken on the current kernel source; else None."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for ln in open(TRAFFIC_FILE):
+        if ":" in ln and not ln.startswith("#"):
+            k, v = ln.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_source_sha256") != kernel_source_sha():
+        return None
+    try:
+        return float(vals["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def time_launches(fn, steps, warmup, torch):
+    """Run fn() warmup times, then `steps` times with a HIP event pair around each launch
+    on the current stream (the stream the library launches on).  Returns
+    (ms_per_step over the whole timed region, list of per-launch ms)."""
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    evs[0].record(stream)
+    for i in range(steps):
+        fn()
+        evs[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per = [evs[i].elapsed_time(evs[i + 1]) for i in range(steps)]
+    return evs[0].elapsed_time(evs[-1]) / steps, per
+
+
+def cpu_baseline(D, G, u, min_seconds=10.0, max_reps=1000):
+    """The FP64 oracle on the host cores, on the first elements of the same workload."""
+    import oracle
+    K, F, Np = u.shape
+    oracle.volume(D, G[:64], u[:64])  # load/compile outside the timing
+    reps, t0 = 0, time.perf_counter()
+    while True:
+        oracle.volume(D, G, u)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= min_seconds or reps >= max_reps:
+            break
+    return {"value": round(reps * K * F * Np / el / 1e9, 4), "unit": "GDOF/s",
+            "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"first {K} of 1048576 elements (order 4, F=5), {reps} pass(es) in {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-forms", action="store_true", help="skip the split-BF16 and adjoint lines")
+    ap.add_argument("--cpu-elements", type=int, default=1 << 18)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the volume kernel "
+              "needs no communication; the multi-GPU split is a partition of the elements.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1503_07659_amd import dgvol, setup_host, synth
+
+    N, K, F = 4, 1 << 20, 5
+    Np = setup_host.NODE_COUNTS[N]
+    D = setup_host.reference_matrices(N)
+    G = setup_host.geometric_factors(synth.tet_vertices(K, synth.mesh_seed(2)))
+    u = synth.fields(K, F, Np, synth.field_seed(2), "normal")
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    Dd, Gd, ud = (torch.from_numpy(x).to(dev) for x in (D, G, u))
+    out = torch.empty((3, K, F, Np), dtype=torch.float64, device=dev)
+
+    def step():
+        dgvol.dg_volume(Dd, Gd, ud, out=out)
+
+    ms, per = time_launches(step, args.steps, args.warmup, torch)
+    kern_ms = float(np.mean(per))
+    dofs = K * F * Np
+    bytes_launch = K * fwd_bytes_per_element(F, Np)
+    flops_launch = K * fwd_flops_per_element(F, Np)
+    achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
+    rec = {
+        "metric": METRIC,
+        "value": round(dofs / (ms * 1e-3) / 1e9, 3),
+        "unit": "GDOF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "fp64_order4_K1048576_F5", "order": N, "Np": Np, "K": K, "F": F,
+                   "u": "N(0,1)", "mesh": "unit tet + U(-0.2,0.2) vertex jitter"},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(),
+                     "kernel_ms": round(kern_ms, 5),
+                     "fp64_tflops": round(flops_launch / (kern_ms * 1e-3) / 1e12, 2),
+                     "fp64_frac": round(flops_launch / (kern_ms * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)},
+    }
+    del out
+    torch.cuda.empty_cache()
+
+    if not args.no_forms:
+        forms = {}
+        # chosen precision form at the same shape: FP32 storage, split-BF16 products
+        D32, G32, u32 = (torch.from_numpy(x.astype(np.float32)).to(dev) for x in (D, G, u))
+        o32 = torch.empty((3, K, F, Np), dtype=torch.float32, device=dev)
+        ms32, per32 = time_launches(lambda: dgvol.dg_volume_f32s(D32, G32, u32, out=o32), 20, 3, torch)
+        k32 = float(np.mean(per32))
+        forms["f32s_split_bf16_same_workload"] = {
+            "GDOF/s": round(dofs / (ms32 * 1e-3) / 1e9, 3), "kernel_ms": round(k32, 5),
+            "hbm_GBs": round(K * fwd_bytes_per_element(F, Np, 4) / (k32 * 1e-3) / 1e9, 1),
+            "hbm_frac": round(K * fwd_bytes_per_element(F, Np, 4) / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "speedup_vs_fp64": round(ms / ms32, 3)}
+        del D32, G32, u32, o32, Dd, Gd, ud
+        torch.cuda.empty_cache()
+        # adjoint workload: order 5, K = 2^19, F = 3, gout = 2 out
+        N5, K5, F5 = 5, 1 << 19, 3
+        Np5 = setup_host.NODE_COUNTS[N5]
+        D5 = torch.from_numpy(setup_host.reference_matrices(N5)).to(dev)
+        G5 = torch.from_numpy(setup_host.geometric_factors(synth.tet_vertices(K5, synth.mesh_seed(5)))).to(dev)
+        u5 = torch.from_numpy(synth.fields(K5, F5, Np5, synth.field_seed(5), "uniform")).to(dev)
+        o5 = torch.empty((3, K5, F5, Np5), dtype=torch.float64, device=dev)
+        msf, perf = time_launches(lambda: dgvol.dg_volume(D5, G5, u5, out=o5), 20, 3, torch)
+        g5 = 2.0 * o5
+        gu5 = torch.empty_like(u5)
+        gG5 = torch.empty_like(G5)
+        msa, pera = time_launches(lambda: dgvol.dg_volume_adjoint(D5, G5, u5, g5, gu=gu5, gG=gG5), 20, 3, torch)
+        ka, kf = float(np.mean(pera)), float(np.mean(perf))
+        d5 = K5 * F5 * Np5
+        fl_f, fl_a = K5 * fwd_flops_per_element(F5, Np5), K5 * adj_flops_per_element(F5, Np5)
+        forms["fp64_order5_K524288_F3"] = {
+            "forward_GDOF/s": round(d5 / (msf * 1e-3) / 1e9, 3), "forward_kernel_ms": round(kf, 5),
+            "forward_fp64_frac": round(fl_f / (kf * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
+            "forward_hbm_frac": round(K5 * fwd_bytes_per_element(F5, Np5) / (kf * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "adjoint_GDOF/s": round(d5 / (msa * 1e-3) / 1e9, 3), "adjoint_kernel_ms": round(ka, 5),
+            "adjoint_fp64_frac": round(fl_a / (ka * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
+            "adjoint_hbm_frac": round(K5 * adj_bytes_per_element(F5, Np5) / (ka * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        rec["forms"] = forms
+
+    if not args.no_cpu:
+        n = min(args.cpu_elements, K)
+        rec["cpu_baseline"] = cpu_baseline(D, G[:n], u[:n])
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

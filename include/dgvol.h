@@ -1,0 +1,111 @@
+/*
+ * dgvol -- nodal discontinuous-Galerkin volume derivative on MI355X (gfx950).
+ *
+ * The volume term of a nodal DG discretisation on affine tetrahedra (the
+ * PDE-solver use case the paper lists in its Introduction as one of the
+ * workloads that shaped its design).  For every element k and field f:
+ *
+ *     R_a[i]   = sum_j D[a][i][j] * u[k][f][j]        a in {r, s, t}
+ *     out_b[i] = sum_a G[k][3a+b] * R_a[i]            b in {x, y, z}
+ *
+ * D are the reference differentiation matrices of the order-N element
+ * (Np = (N+1)(N+2)(N+3)/6 nodes) and G[k] = J_k^{-1} are the element's
+ * geometric factors (d r_a / d x_b).  The paper states no formulas for this
+ * kernel; the definitions above are the standard chain rule for an affine
+ * element.  Of the paper's transformations, the staging of D on chip is its
+ * precompute of a repeatedly fetched operand (Section "Substitution rules
+ * for precomputation"), and the product itself is the dense matrix-matrix
+ * multiplication of its second worked example ("Some examples").
+ *
+ * Array layouts (dense, row-major, caller-owned device memory):
+ *   D    [3][Np][Np]      D_r, D_s, D_t
+ *   G    [K][9]           rx ry rz sx sy sz tx ty tz  (G[k][3a+b] = d r_a / d x_b)
+ *   u    [K][F][Np]       element-major nodal values
+ *   out  [3][K][F][Np]    the d/dx, d/dy, d/dz planes
+ *
+ * Conventions shared by every entry point:
+ *   - All pointers are device pointers except where stated; the caller owns
+ *     every buffer; the library allocates no device memory.
+ *   - Calls are asynchronous and ordered on `stream` (a hipStream_t; NULL is
+ *     the null stream).  Nothing synchronises the host.
+ *   - Outputs are overwritten, never accumulated.  Outputs must not overlap
+ *     any input or each other.
+ *   - Arguments are validated before any HIP call; on error nothing is
+ *     launched and no output is touched.
+ *   - K == 0 is a no-op that returns DG_OK (pointers may then be NULL).
+ *   - Pointers must be aligned to their element size (8 bytes for double,
+ *     4 bytes for float).
+ *   - Supported node counts: Np in {4, 10, 20, 35, 56, 84, 120} (N = 1..7).
+ *   - Results depend only on the inputs and Np/F, not on launch timing:
+ *     repeated calls give bitwise identical outputs.
+ */
+#ifndef DGVOL_H
+#define DGVOL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t dg_status;
+
+#define DG_OK 0
+#define DG_EINVAL (-1)        /* null pointer, K < 0, F < 1, misaligned pointer, bad size */
+#define DG_EUNSUPPORTED (-2)  /* Np not a supported node count, or form not available */
+#define DG_ELAUNCH (-3)       /* the HIP launch reported an error */
+#define DG_EDEVICE (-4)       /* querying the current device failed */
+
+#define DGVOL_ABI_VERSION 1
+
+/* Version of this interface (DGVOL_ABI_VERSION of the built library). */
+int32_t dg_abi_version(void);
+
+/* Static description of a status code; never NULL. */
+const char *dg_strerror(dg_status status);
+
+/* 1 if Np is a supported node count, else 0. */
+int32_t dg_supported_np(int32_t Np);
+
+/*
+ * Forward volume derivative in FP64.
+ *   D    [3][Np][Np]   reference differentiation matrices (read)
+ *   G    [K][9]        geometric factors (read)
+ *   u    [K][F][Np]    nodal values (read)
+ *   out  [3][K][F][Np] written: out[b][k][f][i] = sum_a G[k][3a+b] (D_a u[k][f])[i]
+ * Errors: DG_EINVAL (null pointer with K > 0, K < 0, F < 1, misaligned),
+ *         DG_EUNSUPPORTED (Np), DG_ELAUNCH.
+ */
+dg_status dg_volume(const double *D, const double *G, const double *u, double *out,
+                    int64_t K, int32_t Np, int32_t F, void *stream);
+
+/*
+ * Adjoint (reverse mode) of dg_volume with respect to u and G, FP64.
+ * Given the cotangent gout of out:
+ *   gu[k][f][j]  = sum_a sum_i D[a][i][j] * W_a[i],  W_a[i] = sum_b G[k][3a+b] gout[b][k][f][i]
+ *   gG[k][3a+b]  = sum_f sum_i gout[b][k][f][i] * (D_a u[k][f])[i]
+ *   gout [3][K][F][Np] (read), gu [K][F][Np] (written), gG [K][9] (written).
+ * D_a u is recomputed, not read.  Errors as for dg_volume.
+ */
+dg_status dg_volume_adjoint(const double *D, const double *G, const double *u,
+                            const double *gout, double *gu, double *gG,
+                            int64_t K, int32_t Np, int32_t F, void *stream);
+
+/*
+ * Forward volume derivative with FP32 storage and split-BF16 products.
+ * Same layouts as dg_volume with float elements.  Each FP32 operand x of the
+ * product D_a u is split into x_hi = bf16(x) and x_lo = bf16(x - x_hi)
+ * (round to nearest even); D_a u is formed as D_hi u_hi + D_hi u_lo + D_lo u_hi
+ * on BF16 matrix cores with FP32 accumulation, and the G combine runs in FP32.
+ * Accuracy: see the library documentation of the stated error bound
+ * (normwise max relative error per plane <= 2e-5, RMS <= 1e-5 against FP64).
+ * Errors as for dg_volume.
+ */
+dg_status dg_volume_f32s(const float *D, const float *G, const float *u, float *out,
+                         int64_t K, int32_t Np, int32_t F, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DGVOL_H */

@@ -1,0 +1,185 @@
+"""Python binding of libdgvol.so (argument marshalling only).
+
+The functions named like the C entry points (``dg_volume``,
+``dg_volume_adjoint``, ``dg_volume_f32s``) take torch tensors on the GPU,
+check dtype/device/shape/contiguity, and pass raw device pointers plus torch's
+current HIP stream to the library.  Every arithmetic step runs in the HIP
+kernels; there is no CPU or PyTorch fallback: if the library is missing or
+fails to load, every call raises.
+
+``DGVolume`` is a ``torch.autograd.Function`` whose backward calls the adjoint
+kernel (gradients with respect to u and G; D is treated as a constant).
+"""
+
+import ctypes
+import os
+
+import torch
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdgvol.so")
+
+DG_OK = 0
+DG_EINVAL = -1
+DG_EUNSUPPORTED = -2
+DG_ELAUNCH = -3
+DG_EDEVICE = -4
+
+SUPPORTED_NP = (4, 10, 20, 35, 56, 84, 120)
+
+_lib = None
+
+
+class DGVolError(RuntimeError):
+    """A library call returned a negative status."""
+
+    def __init__(self, status, msg):
+        super().__init__(f"{msg} (status {status})")
+        self.status = status
+
+
+def load_library(path=None):
+    """Load libdgvol.so (once).  Raises RuntimeError if it is not built."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"HIP library {p} is not built; run `python -m paper_1503_07659_amd.build`")
+    lib = ctypes.CDLL(p)
+    P, I64, I32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    lib.dg_abi_version.argtypes = []
+    lib.dg_abi_version.restype = I32
+    lib.dg_strerror.argtypes = [I32]
+    lib.dg_strerror.restype = ctypes.c_char_p
+    lib.dg_supported_np.argtypes = [I32]
+    lib.dg_supported_np.restype = I32
+    lib.dg_volume.argtypes = [P, P, P, P, I64, I32, I32, P]
+    lib.dg_volume.restype = I32
+    lib.dg_volume_adjoint.argtypes = [P, P, P, P, P, P, I64, I32, I32, P]
+    lib.dg_volume_adjoint.restype = I32
+    lib.dg_volume_f32s.argtypes = [P, P, P, P, I64, I32, I32, P]
+    lib.dg_volume_f32s.restype = I32
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def strerror(status):
+    return load_library().dg_strerror(int(status)).decode()
+
+
+def _raise_on(status, what):
+    if status != DG_OK:
+        raise DGVolError(status, f"{what}: {strerror(status)}")
+
+
+def _stream_handle(device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def _check_tensor(name, t, dtype, shape, device=None):
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch.Tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be on a GPU, got {t.device}")
+    if device is not None and t.device != device:
+        raise ValueError(f"{name} is on {t.device}, expected {device}")
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def _sizes(u, D):
+    if u.dim() != 3:
+        raise ValueError(f"u must be (K, F, Np), got shape {tuple(u.shape)}")
+    K, F, Np = u.shape
+    if Np not in SUPPORTED_NP:
+        raise ValueError(f"unsupported node count Np={Np}; supported: {SUPPORTED_NP}")
+    return K, F, Np
+
+
+def dg_volume(D, G, u, out=None):
+    """FP64 forward: out[b,k,f,i] = sum_a G[k,3a+b] (D_a u[k,f])[i]; returns out (3, K, F, Np)."""
+    K, F, Np = _sizes(u, D)
+    dev = u.device
+    _check_tensor("u", u, torch.float64, (K, F, Np))
+    _check_tensor("D", D, torch.float64, (3, Np, Np), dev)
+    _check_tensor("G", G, torch.float64, (K, 9), dev)
+    if out is None:
+        out = torch.empty((3, K, F, Np), dtype=torch.float64, device=dev)
+    _check_tensor("out", out, torch.float64, (3, K, F, Np), dev)
+    with torch.cuda.device(dev):
+        st = load_library().dg_volume(D.data_ptr(), G.data_ptr(), u.data_ptr(), out.data_ptr(),
+                                      K, Np, F, _stream_handle(dev))
+    _raise_on(st, "dg_volume")
+    return out
+
+
+def dg_volume_adjoint(D, G, u, gout, gu=None, gG=None):
+    """FP64 adjoint w.r.t. u and G for the cotangent gout (3, K, F, Np); returns (gu, gG)."""
+    K, F, Np = _sizes(u, D)
+    dev = u.device
+    _check_tensor("u", u, torch.float64, (K, F, Np))
+    _check_tensor("D", D, torch.float64, (3, Np, Np), dev)
+    _check_tensor("G", G, torch.float64, (K, 9), dev)
+    _check_tensor("gout", gout, torch.float64, (3, K, F, Np), dev)
+    if gu is None:
+        gu = torch.empty((K, F, Np), dtype=torch.float64, device=dev)
+    if gG is None:
+        gG = torch.empty((K, 9), dtype=torch.float64, device=dev)
+    _check_tensor("gu", gu, torch.float64, (K, F, Np), dev)
+    _check_tensor("gG", gG, torch.float64, (K, 9), dev)
+    with torch.cuda.device(dev):
+        st = load_library().dg_volume_adjoint(D.data_ptr(), G.data_ptr(), u.data_ptr(), gout.data_ptr(),
+                                              gu.data_ptr(), gG.data_ptr(), K, Np, F, _stream_handle(dev))
+    _raise_on(st, "dg_volume_adjoint")
+    return gu, gG
+
+
+def dg_volume_f32s(D, G, u, out=None):
+    """FP32 storage, split-BF16 products: same contract as dg_volume with float32 tensors."""
+    K, F, Np = _sizes(u, D)
+    dev = u.device
+    _check_tensor("u", u, torch.float32, (K, F, Np))
+    _check_tensor("D", D, torch.float32, (3, Np, Np), dev)
+    _check_tensor("G", G, torch.float32, (K, 9), dev)
+    if out is None:
+        out = torch.empty((3, K, F, Np), dtype=torch.float32, device=dev)
+    _check_tensor("out", out, torch.float32, (3, K, F, Np), dev)
+    with torch.cuda.device(dev):
+        st = load_library().dg_volume_f32s(D.data_ptr(), G.data_ptr(), u.data_ptr(), out.data_ptr(),
+                                           K, Np, F, _stream_handle(dev))
+    _raise_on(st, "dg_volume_f32s")
+    return out
+
+
+class DGVolume(torch.autograd.Function):
+    """out = dg_volume(D, G, u) with gradients for u and G from the adjoint kernel.
+
+    Call as ``DGVolume.apply(u, G, D)``.  D receives no gradient.
+    """
+
+    @staticmethod
+    def forward(ctx, u, G, D):
+        u = u.contiguous()
+        G = G.contiguous()
+        D = D.contiguous()
+        ctx.save_for_backward(u, G, D)
+        return dg_volume(D, G, u)
+
+    @staticmethod
+    def backward(ctx, gout):
+        u, G, D = ctx.saved_tensors
+        gu, gG = dg_volume_adjoint(D, G, u, gout.contiguous())
+        return (gu if ctx.needs_input_grad[0] else None,
+                gG if ctx.needs_input_grad[1] else None,
+                None)
+
+
+def volume(u, G, D):
+    """Differentiable forward volume derivative (FP64): ``DGVolume.apply(u, G, D)``."""
+    return DGVolume.apply(u, G, D)

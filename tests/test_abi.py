@@ -1,0 +1,120 @@
+"""The C ABI without a GPU: the library loads, exports every declared entry point,
+and rejects bad arguments before making any HIP call.  Also the host-side setup
+helpers of the library against the oracle."""
+
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle.exact import exact_derivative_matrices_f64
+from paper_1503_07659_amd import dgvol, setup_host, synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "dgvol.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(dg_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(dgvol.LIB_PATH):
+        pytest.fail("libdgvol.so is not built: run `python -m paper_1503_07659_amd.build`")
+    return dgvol.load_library()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for required in ("dg_volume", "dg_volume_adjoint", "dg_volume_f32s", "dg_strerror",
+                     "dg_supported_np", "dg_abi_version"):
+        assert required in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), f"{name} declared in dgvol.h but not exported"
+
+
+def test_version_and_strerror(lib):
+    assert lib.dg_abi_version() == 1
+    for st in (0, -1, -2, -3, -4, -99):
+        msg = lib.dg_strerror(st)
+        assert isinstance(msg, bytes) and msg
+    assert [lib.dg_supported_np(n) for n in (4, 10, 20, 35, 56, 84, 120)] == [1] * 7
+    assert [lib.dg_supported_np(n) for n in (0, 1, 5, 21, 36, 121, -4)] == [0] * 7
+
+
+FAKE = 0x100000  # a non-null, 256-byte aligned address that is never dereferenced
+
+
+@pytest.mark.parametrize("entry", ["dg_volume", "dg_volume_f32s"])
+def test_forward_validation(lib, entry):
+    f = getattr(lib, entry)
+    s = None
+    assert f(FAKE, FAKE, FAKE, FAKE, 0, 35, 5, s) == dgvol.DG_OK           # K == 0: no-op
+    assert f(None, None, None, None, 0, 35, 5, s) == dgvol.DG_OK           # ... even with NULLs
+    assert f(FAKE, FAKE, FAKE, FAKE, -1, 35, 5, s) == dgvol.DG_EINVAL
+    assert f(FAKE, FAKE, FAKE, FAKE, 10, 35, 0, s) == dgvol.DG_EINVAL
+    assert f(FAKE, FAKE, FAKE, FAKE, 10, 36, 5, s) == dgvol.DG_EUNSUPPORTED
+    assert f(FAKE, FAKE, FAKE, FAKE, 10, 0, 5, s) == dgvol.DG_EUNSUPPORTED
+    for i in range(4):
+        ptrs = [FAKE] * 4
+        ptrs[i] = None
+        assert f(*ptrs, 10, 35, 5, s) == dgvol.DG_EINVAL
+        ptrs[i] = FAKE + 2  # misaligned for both float and double
+        assert f(*ptrs, 10, 35, 5, s) == dgvol.DG_EINVAL
+    assert f(FAKE, FAKE, FAKE, FAKE, 1 << 30, 35, 4, s) == dgvol.DG_EINVAL  # K*F >= 2^31
+
+
+def test_adjoint_validation(lib):
+    f = lib.dg_volume_adjoint
+    assert f(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 0, 56, 3, None) == dgvol.DG_OK
+    assert f(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, -5, 56, 3, None) == dgvol.DG_EINVAL
+    assert f(FAKE, FAKE, FAKE, FAKE, FAKE, FAKE, 5, 57, 3, None) == dgvol.DG_EUNSUPPORTED
+    for i in range(6):
+        ptrs = [FAKE] * 6
+        ptrs[i] = None
+        assert f(*ptrs, 5, 56, 3, None) == dgvol.DG_EINVAL
+        ptrs[i] = FAKE + 4
+        assert f(*ptrs, 5, 56, 3, None) == dgvol.DG_EINVAL
+
+
+def test_python_binding_rejects_cpu_tensors():
+    import torch
+    u = torch.zeros((4, 1, 20), dtype=torch.float64)
+    D = torch.zeros((3, 20, 20), dtype=torch.float64)
+    G = torch.zeros((4, 9), dtype=torch.float64)
+    with pytest.raises(ValueError):
+        dgvol.dg_volume(D, G, u)
+    with pytest.raises(TypeError):
+        dgvol.dg_volume(D, G, u.float())
+    with pytest.raises(ValueError):
+        dgvol.dg_volume(D, G, torch.zeros((4, 1, 21), dtype=torch.float64))
+
+
+# ----------------------------------------------------- host setup of the library vs the oracle
+
+@pytest.mark.parametrize("N", range(1, 8))
+def test_library_reference_matrices(N):
+    D = setup_host.reference_matrices(N)
+    E = np.array(exact_derivative_matrices_f64(N))
+    assert D.shape == (3, oracle.num_nodes(N), oracle.num_nodes(N))
+    # centred monomials: measured 8e-15 (N=5), 1.7e-13 (N=7) relative to max|D|
+    assert np.abs(D - E).max() <= 1e-12 * np.abs(E).max()
+    assert np.array_equal(setup_host.reference_nodes(N), oracle.equispaced_nodes(N))
+
+
+def test_library_geometric_factors():
+    v = synth.tet_vertices(2000, seed=17)
+    assert np.abs(setup_host.geometric_factors(v) - oracle.geometric_factors(v)).max() < 1e-14
+    bad = v.copy()
+    bad[5, 3] = bad[5, 0]
+    with pytest.raises(ValueError):
+        setup_host.geometric_factors(bad)
