@@ -8,12 +8,21 @@ headline workload: order 4 (Np = 35), K = 2^20 jittered affine tetrahedra,
 F = 5 fields u ~ N(0,1), element-major FP64, inputs resident in HBM.
 
 Prints one JSON line: GDOF/s (K F Np per second), the HBM roofline of the
-kernel measured with HIP events on the launch stream, the FP64 oracle timed on
-the host cores on a bounded sample, and the split-BF16 form and the adjoint
-measured beside it.
+kernel measured with HIP events on the launch stream, the measured streaming
+ceiling for the kernel's read/write mix, the FP64 oracle timed on the host
+cores on a bounded sample, and the split-BF16 form and the adjoint measured
+beside it.
+
+Profiling helpers (used to produce the committed counter summaries):
+    python bench.py --profile-run                  # 1 GiB copy x3, then the forward kernel x3
+    python bench.py --summarize-counters FETCH_DIR WRITE_DIR
+        # reads two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` output trees of
+        # --profile-run and writes the HBM traffic summary under profiles/
 """
 
 import argparse
+import csv
+import glob
 import hashlib
 import json
 import os
@@ -28,9 +37,12 @@ sys.path.insert(0, ROOT)
 METRIC = "DG volume GDOF/s + % HBM/MFMA roofline; plain FP64 vs chosen form"
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFS = 78.6           # MI355X FP64 (vector and matrix)
-BF16_PEAK_TFS = 2500.0         # MI355X dense BF16 matrix
-KERNEL_SRC = os.path.join(ROOT, "paper_1503_07659_amd", "csrc", "dgvol_kernels.hip")
+KERNEL_SRC_DIR = os.path.join(ROOT, "paper_1503_07659_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dg_volume_fwd_f64_order4_K1048576_F5.txt")
+FWD_KERNEL_TAG = "fwd_f64_kernel<35, 0>"
+COPY_KERNEL_TAG = "stream_kernel"
+WORKLOAD = dict(N=4, K=1 << 20, F=5)
+PROFILE_COPY_DOUBLES = 1 << 27  # 1 GiB copy for counter calibration
 
 
 def fwd_bytes_per_element(F, Np, word=8):
@@ -53,13 +65,19 @@ def adj_flops_per_element(F, Np):
 
 
 def kernel_source_sha():
-    with open(KERNEL_SRC, "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()
+    """SHA-256 over every kernel source file (sorted by name)."""
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(KERNEL_SRC_DIR)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(name.encode())
+            with open(os.path.join(KERNEL_SRC_DIR, name), "rb") as fh:
+                h.update(fh.read())
+    return h.hexdigest()
 
 
 def recorded_traffic():
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if it was
-    taken on the current kernel source; else None."""
+    """HBM bytes per launch of the forward kernel from the committed counter summary, if it
+    was taken on the current kernel source; else None."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -107,7 +125,97 @@ def cpu_baseline(D, G, u, min_seconds=10.0, max_reps=1000):
             break
     return {"value": round(reps * K * F * Np / el / 1e9, 4), "unit": "GDOF/s",
             "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": f"first {K} of 1048576 elements (order 4, F=5), {reps} pass(es) in {el:.1f} s"}
+            "sample": f"first {K} of {WORKLOAD['K']} elements (order 4, F=5), {reps} pass(es) in {el:.1f} s"}
+
+
+def workload_inputs():
+    from paper_1503_07659_amd import setup_host, synth
+    N, K, F = WORKLOAD["N"], WORKLOAD["K"], WORKLOAD["F"]
+    Np = setup_host.NODE_COUNTS[N]
+    D = setup_host.reference_matrices(N)
+    G = setup_host.geometric_factors(synth.tet_vertices(K, synth.mesh_seed(2)))
+    u = synth.fields(K, F, Np, synth.field_seed(2), "normal")
+    return D, G, u
+
+
+def profile_run():
+    """Known-size copy (counter scale) followed by the forward kernel, three launches each."""
+    import torch
+    from paper_1503_07659_amd import dgvol
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    src = torch.ones(PROFILE_COPY_DOUBLES, dtype=torch.float64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dgvol.dg_stream_calibrate(src, dst, 1)
+    torch.cuda.synchronize()
+    del src, dst
+    D, G, u = workload_inputs()
+    Dd, Gd, ud = (torch.from_numpy(x).to(dev) for x in (D, G, u))
+    out = torch.empty((3,) + tuple(u.shape), dtype=torch.float64, device=dev)
+    for _ in range(3):
+        dgvol.dg_volume(Dd, Gd, ud, out=out)
+    torch.cuda.synchronize()
+    print("profile run done", flush=True)
+
+
+def _counter_rows(root):
+    rows = []
+    for path in glob.glob(os.path.join(root, "**", "*counter_collection*.csv"), recursive=True):
+        with open(path, newline="") as fh:
+            rows.extend(csv.DictReader(fh))
+    if not rows:
+        raise SystemExit(f"no counter_collection csv under {root}")
+    return rows
+
+
+def _per_dispatch(rows, counter, tag):
+    vals = {}
+    for r in rows:
+        if r.get("Counter_Name") != counter or tag not in r.get("Kernel_Name", ""):
+            continue
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        vals[key] = vals.get(key, 0.0) + float(r["Counter_Value"])
+    return [vals[k] for k in sorted(vals, key=lambda x: int(x))]
+
+
+def summarize_counters(fetch_dir, write_dir):
+    fr, wr = _counter_rows(fetch_dir), _counter_rows(write_dir)
+    cf = _per_dispatch(fr, "FETCH_SIZE", COPY_KERNEL_TAG)
+    cw = _per_dispatch(wr, "WRITE_SIZE", COPY_KERNEL_TAG)
+    kf = _per_dispatch(fr, "FETCH_SIZE", FWD_KERNEL_TAG)
+    kw = _per_dispatch(wr, "WRITE_SIZE", FWD_KERNEL_TAG)
+    if not (cf and cw and kf and kw):
+        raise SystemExit("missing dispatches of the copy or the forward kernel in the counter output")
+    copy_bytes = PROFILE_COPY_DOUBLES * 8
+    sf = copy_bytes / float(np.median(cf))   # bytes per counter unit, read side
+    sw = copy_bytes / float(np.median(cw))   # bytes per counter unit, write side
+    fetch_b = float(np.median(kf)) * sf
+    write_b = float(np.median(kw)) * sw
+    N, K, F = WORKLOAD["N"], WORKLOAD["K"], WORKLOAD["F"]
+    Np = (N + 1) * (N + 2) * (N + 3) // 6
+    alg = K * fwd_bytes_per_element(F, Np)
+    os.makedirs(os.path.dirname(TRAFFIC_FILE), exist_ok=True)
+    with open(TRAFFIC_FILE, "w") as fh:
+        fh.write("# HBM traffic of dg_volume (FP64 staged forward kernel), order 4, K=2^20, F=5.\n")
+        fh.write("# Two rocprofv3 counter passes over `python bench.py --profile-run`:\n")
+        fh.write("#   rocprofv3 --pmc FETCH_SIZE -d <fetch_dir> --output-format csv -- python bench.py --profile-run\n")
+        fh.write("#   rocprofv3 --pmc WRITE_SIZE -d <write_dir> --output-format csv -- python bench.py --profile-run\n")
+        fh.write("#   python bench.py --summarize-counters <fetch_dir> <write_dir>\n")
+        fh.write("# Counter units are scaled by a 1 GiB copy (stream_kernel, copies=1) in the same runs.\n")
+        fh.write(f"kernel_source_sha256: {kernel_source_sha()}\n")
+        fh.write(f"copy_fetch_counter_per_launch: {np.median(cf):.1f}\n")
+        fh.write(f"copy_write_counter_per_launch: {np.median(cw):.1f}\n")
+        fh.write(f"fetch_scale_bytes_per_unit: {sf:.4f}\n")
+        fh.write(f"write_scale_bytes_per_unit: {sw:.4f}\n")
+        fh.write(f"kernel_fetch_counter_per_launch: {np.median(kf):.1f}\n")
+        fh.write(f"kernel_write_counter_per_launch: {np.median(kw):.1f}\n")
+        fh.write(f"fetch_bytes_per_launch: {fetch_b:.0f}\n")
+        fh.write(f"write_bytes_per_launch: {write_b:.0f}\n")
+        fh.write(f"hbm_bytes_per_launch: {fetch_b + write_b:.0f}\n")
+        fh.write(f"algorithmic_bytes_per_launch: {alg}\n")
+        fh.write(f"traffic_over_algorithmic: {(fetch_b + write_b) / alg:.4f}\n")
+    print(open(TRAFFIC_FILE).read())
 
 
 def main():
@@ -118,21 +226,27 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-forms", action="store_true", help="skip the split-BF16 and adjoint lines")
     ap.add_argument("--cpu-elements", type=int, default=1 << 18)
+    ap.add_argument("--profile-run", action="store_true")
+    ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
     args = ap.parse_args()
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the volume kernel "
               "needs no communication; the multi-GPU split is a partition of the elements.",
               file=sys.stderr)
         sys.exit(2)
+    if args.profile_run:
+        profile_run()
+        return
 
     import torch
     from paper_1503_07659_amd import dgvol, setup_host, synth
 
-    N, K, F = 4, 1 << 20, 5
+    N, K, F = WORKLOAD["N"], WORKLOAD["K"], WORKLOAD["F"]
     Np = setup_host.NODE_COUNTS[N]
-    D = setup_host.reference_matrices(N)
-    G = setup_host.geometric_factors(synth.tet_vertices(K, synth.mesh_seed(2)))
-    u = synth.fields(K, F, Np, synth.field_seed(2), "normal")
+    D, G, u = workload_inputs()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     Dd, Gd, ud = (torch.from_numpy(x).to(dev) for x in (D, G, u))
@@ -147,6 +261,14 @@ def main():
     bytes_launch = K * fwd_bytes_per_element(F, Np)
     flops_launch = K * fwd_flops_per_element(F, Np)
     achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
+
+    # practical streaming ceiling for the same bytes in the same 1 : 3 read : write mix
+    n_u = ud.numel()
+    _, per_c = time_launches(lambda: dgvol.dg_stream_calibrate(ud.view(-1), out.view(-1), 3), 10, 2, torch)
+    ceil_gbs = 4 * n_u * 8 / (float(np.median(per_c)) * 1e-3) / 1e9
+    _, per_1 = time_launches(lambda: dgvol.dg_stream_calibrate(ud.view(-1), out.view(-1)[:n_u], 1), 10, 2, torch)
+    copy_gbs = 2 * n_u * 8 / (float(np.median(per_1)) * 1e-3) / 1e9
+
     rec = {
         "metric": METRIC,
         "value": round(dofs / (ms * 1e-3) / 1e9, 3),
@@ -165,6 +287,9 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(),
                      "kernel_ms": round(kern_ms, 5),
+                     "measured_stream_ceiling_1r3w_GBs": round(ceil_gbs, 1),
+                     "frac_of_measured_ceiling": round(achieved / ceil_gbs, 4),
+                     "measured_copy_GBs": round(copy_gbs, 1),
                      "fp64_tflops": round(flops_launch / (kern_ms * 1e-3) / 1e12, 2),
                      "fp64_frac": round(flops_launch / (kern_ms * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)},
     }

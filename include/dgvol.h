@@ -58,6 +58,17 @@ typedef int32_t dg_status;
 
 #define DGVOL_ABI_VERSION 1
 
+/* Forms (precisions) of the forward product. */
+#define DG_FORM_F64 0   /* FP64 storage, FP64 matrix cores */
+#define DG_FORM_F32S 1  /* FP32 storage, split-BF16 matrix cores (see dg_volume_f32s) */
+
+/* Kernel bodies of the forward product (same results, different data movement). */
+#define DG_BODY_AUTO (-1)     /* the library's default for the form and order */
+#define DG_BODY_STAGED 0      /* D in LDS, u and out staged through LDS per wave (memory-bound orders) */
+#define DG_BODY_CHUNKREG 1    /* D held in registers, one output chunk per wave (matrix-core-bound orders) */
+
+#define DG_MAX_GROUPS 16
+
 /* Version of this interface (DGVOL_ABI_VERSION of the built library). */
 int32_t dg_abi_version(void);
 
@@ -97,12 +108,63 @@ dg_status dg_volume_adjoint(const double *D, const double *G, const double *u,
  * product D_a u is split into x_hi = bf16(x) and x_lo = bf16(x - x_hi)
  * (round to nearest even); D_a u is formed as D_hi u_hi + D_hi u_lo + D_lo u_hi
  * on BF16 matrix cores with FP32 accumulation, and the G combine runs in FP32.
- * Accuracy: see the library documentation of the stated error bound
- * (normwise max relative error per plane <= 2e-5, RMS <= 1e-5 against FP64).
+ * Stated accuracy against the FP64 result on the same (FP64) data: per output
+ * plane, max|err| <= 2e-5 max|ref| and ||err||_2 <= 1e-5 ||ref||_2.
  * Errors as for dg_volume.
  */
 dg_status dg_volume_f32s(const float *D, const float *G, const float *u, float *out,
                          int64_t K, int32_t Np, int32_t F, void *stream);
+
+/*
+ * One element group of a mixed-order batch (dg_volume_batched).  All pointers
+ * are device pointers to arrays of the batch's form (double for DG_FORM_F64,
+ * float for DG_FORM_F32S), laid out as for dg_volume.
+ */
+typedef struct dg_group {
+  int32_t Np;          /* node count of the group's order */
+  int32_t body;        /* DG_BODY_AUTO, DG_BODY_STAGED or DG_BODY_CHUNKREG */
+  int64_t K;           /* elements in the group (>= 0; 0 = skip) */
+  const void *D;       /* [3][Np][Np] */
+  const void *G;       /* [K][9] */
+  const void *u;       /* [K][F][Np] */
+  void *out;           /* [3][K][F][Np], written */
+  double cost;         /* measured cost of one 16-column tile, any unit common to the
+                          batch, used to split workgroups between groups; <= 0 selects
+                          the library's roofline estimate */
+} dg_group;
+
+/*
+ * Forward volume derivative of up to DG_MAX_GROUPS element groups of
+ * possibly different orders, sharing F, in ONE persistent kernel launch.
+ * `groups` is a host array of `ngroups` descriptors; it is read during the
+ * call only.  Workgroups are split between groups in proportion to
+ * cost x tiles (a static split: the launch needs no device-side state and can
+ * be captured in a HIP graph).  Each group's out is exactly what dg_volume /
+ * dg_volume_f32s would write for that group alone.
+ * Errors: DG_EINVAL (ngroups outside 0..DG_MAX_GROUPS, F < 1, NULL groups
+ * with ngroups > 0, a group failing the dg_volume argument checks),
+ * DG_EUNSUPPORTED (form, Np or a body not available for the form and order),
+ * DG_EDEVICE, DG_ELAUNCH.  Groups with K = 0 are skipped.
+ */
+dg_status dg_volume_batched(const dg_group *groups, int32_t ngroups, int32_t F, int32_t form, void *stream);
+
+/* 1 if `body` can run `form` at node count Np, else 0. */
+int32_t dg_body_available(int32_t form, int32_t Np, int32_t body);
+
+/* The body DG_BODY_AUTO selects for `form` at node count Np (-1 if unsupported). */
+int32_t dg_default_body(int32_t form, int32_t Np);
+
+/*
+ * Bandwidth calibration (not part of the DG computation).
+ * Reads src[0..n) once and writes `copies` (1..3) scaled copies:
+ * dst[c*n + i] = (c + 1) * src[i]; dst must hold copies * n doubles.
+ * With copies = 1 it is a plain copy of known size, used to scale hardware
+ * byte counters; with copies = 3 it moves bytes in the same 1 : 3 read : write
+ * mix as dg_volume with no other work, which measures the practical streaming
+ * ceiling for that mix.  Errors: DG_EINVAL (n < 0, copies outside 1..3, null
+ * or misaligned pointer with n > 0), DG_EDEVICE, DG_ELAUNCH.
+ */
+dg_status dg_stream_calibrate(const double *src, double *dst, int64_t n, int32_t copies, void *stream);
 
 #ifdef __cplusplus
 }

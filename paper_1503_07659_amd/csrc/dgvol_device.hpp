@@ -1,0 +1,104 @@
+// Device helpers shared by the DG volume kernels: vector types, MFMA operand
+// gathers from D, BF16 splitting, wave-level synchronisation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "dgvol_layout.hpp"
+
+namespace dgvol {
+
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int WAVE = 64;
+
+// Wave-level barrier with LDS visibility (lanes of one wave exchanging data
+// through LDS).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ------------------------------------------------------------------ FP64 A operands
+
+// A operand of output tile T, k-step s, for lane `lane`, read from row-major D.
+// FP64 result rows are 4q + g, so A row m holds slot q = m / 4 of lane group g = m % 4.
+template <int NP>
+__device__ __forceinline__ double afrag_f64(const double* __restrict__ D, int T, int s, int lane) {
+  const int m = lane & 15, kk = lane >> 4;
+  const int q = m >> 2, g = m & 3;
+  const int sigma = 4 * T + q;
+  const int a = slot_dir(sigma), i = slot_node(sigma, g), j = 4 * s + kk;
+  return (sigma < Shape<NP>::SLOTS && i < NP && j < NP) ? D[(a * NP + i) * NP + j] : 0.0;
+}
+
+// A operand of the transposed product (adjoint): tile TJ over output nodes j,
+// k-step sp over the slots of the stacked cotangent W.
+template <int NP>
+__device__ __forceinline__ double afragT_f64(const double* __restrict__ D, int TJ, int sp, int lane) {
+  const int m = lane & 15, kk = lane >> 4;
+  const int j = 16 * TJ + m;
+  const int a = slot_dir(sp), i = slot_node(sp, kk);
+  return (j < NP && i < NP) ? D[(a * NP + i) * NP + j] : 0.0;
+}
+
+template <int NP>
+constexpr int fwd_table_doubles() { return Shape<NP>::MT * Shape<NP>::KS64 * WAVE; }
+
+// XOR swizzle of the A table: entry `lane` of row (T, s) sits at lane ^ ((s & 3) << 2).
+__device__ __forceinline__ int tswz(int lane, int s) { return lane ^ ((s & 3) << 2); }
+
+// ------------------------------------------------------------------ BF16 split
+
+// Round FP32 to the nearest BF16 (ties to even) in integer arithmetic; returns
+// the FP32 bit pattern with the low 16 bits clear.  NaN stays a quiet NaN.
+__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
+  const uint32_t b = __float_as_uint(x);
+  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu) != 0u) return (b | 0x00400000u) & 0xffff0000u;
+  return (b + 0x7fffu + ((b >> 16) & 1u)) & 0xffff0000u;
+}
+
+// x = hi + lo + O(2^-18 |x|): hi = bf16(x), lo = bf16(x - hi), as BF16 bit patterns.
+__device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
+  const uint32_t h = bf16_rne_bits(x);
+  const float r = x - __uint_as_float(h);  // exact in FP32
+  hi = (uint16_t)(h >> 16);
+  lo = (uint16_t)(bf16_rne_bits(r) >> 16);
+}
+
+struct alignas(16) Bf16x8Bits {
+  uint16_t v[8];
+};
+
+__device__ __forceinline__ bf16x8 as_bf16x8(const Bf16x8Bits& x) { return __builtin_bit_cast(bf16x8, x); }
+
+// A operand (8 consecutive k per lane) of tile T, k-step s of the BF16 MFMA,
+// split into hi and lo parts.  BF16 result rows are 4g + q, so A row m holds
+// slot q = m % 4 of lane group g = m / 4.
+template <int NP>
+__device__ __forceinline__ void afrag_bf16(const float* __restrict__ D, int T, int s, int lane,
+                                           Bf16x8Bits& hi, Bf16x8Bits& lo) {
+  const int m = lane & 15, kk = lane >> 4;
+  const int g = m >> 2, q = m & 3;
+  const int sigma = 4 * T + q;
+  const int a = slot_dir(sigma), i = slot_node(sigma, g);
+  const bool row_ok = sigma < Shape<NP>::SLOTS && i < NP;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    const int j = 32 * s + 8 * kk + e;
+    const float x = (row_ok && j < NP) ? D[(a * NP + i) * NP + j] : 0.0f;
+    split_bf16(x, hi.v[e], lo.v[e]);
+  }
+}
+
+template <int NP>
+constexpr int bf16_table_entries() { return Shape<NP>::MT * Shape<NP>::KS16 * WAVE; }
+
+__host__ __device__ constexpr int align16(int bytes) { return (bytes + 15) & ~15; }
+
+}  // namespace dgvol

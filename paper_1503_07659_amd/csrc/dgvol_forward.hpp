@@ -1,0 +1,469 @@
+// Forward bodies of the DG volume derivative (device functions shared by the
+// single-group kernels and the mixed-order batched kernel).
+//
+// out_b[i] = sum_a G[3a+b] (D_a u)[i] for every (element, field) column; a
+// wave computes 16 columns at a time as the stacked product
+// [3Np x Np] . [Np x 16] on the matrix cores with the output rows permuted so
+// that each lane holds (D_r u, D_s u, D_t u) of one node (dgvol_layout.hpp);
+// the geometric-factor combine is then lane-local and fused into the epilogue.
+//
+// Two data-movement schemes:
+//  * staged (memory-bound orders): D lives in LDS as an A-operand table built
+//    once per workgroup (the paper's precompute of a repeatedly fetched
+//    operand into on-chip storage, Section 4.3); every wave owns whole
+//    16-column tiles and moves u in and each output plane out through one LDS
+//    buffer of 16 x Np words, so all global accesses are contiguous runs.
+//  * chunk-register (matrix-core-bound orders, D too large for LDS): the
+//    workgroup shares one 16-column tile; wave w keeps the A operands of output
+//    chunk w (3 tiles) in registers for the whole launch; u is staged once per
+//    tile in LDS and read by all waves; the output planes are assembled in LDS.
+// Each body takes its block index and block count explicitly and carves its
+// LDS from one dynamic buffer, so the same code serves every launch shape.
+#pragma once
+
+#include "dgvol_device.hpp"
+
+namespace dgvol {
+
+template <typename T>
+struct FwdArgs {
+  const T* D;
+  const T* G;
+  const T* u;
+  T* out;
+  uint32_t ncols;   // K * F
+  uint32_t F;
+  int64_t plane;    // K * F * Np (words between output planes)
+  uint32_t ntiles;  // ceil(ncols / 16)
+};
+
+// ------------------------------------------------------------------ FP64 staged
+
+template <int NP, int WPB>
+constexpr int fwd_f64_staged_lds() { return align16(fwd_table_doubles<NP>() * 8) + WPB * 16 * NP * 8; }
+
+template <int NP, int WPB>
+__device__ __forceinline__ void fwd_f64_staged_body(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
+                                                    char* lds) {
+  using Sh = Shape<NP>;
+  constexpr int NFRAG = fwd_table_doubles<NP>();
+  constexpr int TILE = 16 * NP;
+  constexpr int NRAW = (TILE + WAVE - 1) / WAVE;
+  double* afr = reinterpret_cast<double*>(lds);
+  double* stg_all = reinterpret_cast<double*>(lds + align16(NFRAG * 8));
+  for (int e = threadIdx.x; e < NFRAG; e += WAVE * WPB) {
+    const int ts = e >> 6;
+    afr[e] = afrag_f64<NP>(p.D, ts / Sh::KS64, ts % Sh::KS64, e & 63);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const uint32_t wave = threadIdx.x >> 6;
+  double* stg = stg_all + wave * TILE;
+  const uint32_t stride = nblk * WPB;
+  uint32_t t = bid * WPB + wave;
+  double raw[NRAW];
+  auto load_raw = [&](uint32_t tt) {
+    const double* __restrict__ src = p.u + (int64_t)tt * TILE;
+    const int cnt = (int)min(16u, p.ncols - tt * 16) * NP;
+#pragma unroll
+    for (int q = 0; q < NRAW; ++q) {
+      const int x = lane + WAVE * q;
+      raw[q] = x < cnt ? src[x] : 0.0;
+    }
+  };
+  if (t < p.ntiles) load_raw(t);
+  for (; t < p.ntiles; t += stride) {
+    const uint32_t col0 = t * 16;
+    const int cnt = (int)min(16u, p.ncols - col0) * NP;
+#pragma unroll
+    for (int q = 0; q < NRAW; ++q) {
+      const int x = lane + WAVE * q;
+      if (x < TILE) stg[x] = raw[q];
+    }
+    wave_sync();
+    double b[Sh::KS64];
+#pragma unroll
+    for (int s = 0; s < Sh::KS64; ++s) {
+      const int j = 4 * s + g;
+      b[s] = j < NP ? stg[n * NP + j] : 0.0;
+    }
+    const uint32_t col = col0 + n;
+    const bool valid = col < p.ncols;
+    const uint32_t k = valid ? col / p.F : 0u;
+    double gk[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) gk[c] = valid ? p.G[(int64_t)k * 9 + c] : 0.0;
+    wave_sync();
+    f64x4 acc[Sh::MT];
+#pragma unroll
+    for (int T = 0; T < Sh::MT; ++T) acc[T] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // A operands are read one k-step ahead of the products that use them; the
+    // scheduling barrier keeps the compiler from hoisting every read (which
+    // would cost about two registers per MFMA).
+    double a_cur[Sh::MT], a_nxt[Sh::MT];
+#pragma unroll
+    for (int T = 0; T < Sh::MT; ++T) a_cur[T] = afr[(T * Sh::KS64) * WAVE + lane];
+#pragma unroll
+    for (int s = 0; s < Sh::KS64; ++s) {
+#pragma unroll
+      for (int T = 0; T < Sh::MT; ++T) {
+        if (s + 1 < Sh::KS64) a_nxt[T] = afr[(T * Sh::KS64 + s + 1) * WAVE + lane];
+        acc[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[T], b[s], acc[T], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int T = 0; T < Sh::MT; ++T) a_cur[T] = a_nxt[T];
+    }
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+#pragma unroll
+      for (int tau = 0; tau < Sh::TRIP; ++tau) {
+        const int i = 4 * tau + g;
+        const int s0 = 3 * tau;
+        const double v = gk[bb] * acc[s0 >> 2][s0 & 3] + gk[3 + bb] * acc[(s0 + 1) >> 2][(s0 + 1) & 3] +
+                         gk[6 + bb] * acc[(s0 + 2) >> 2][(s0 + 2) & 3];
+        if (i < NP) stg[n * NP + i] = v;
+      }
+      wave_sync();
+      double* __restrict__ ob = p.out + bb * p.plane + (int64_t)col0 * NP;
+#pragma unroll
+      for (int q = 0; q < NRAW; ++q) {
+        const int x = lane + WAVE * q;
+        if (x < cnt) ob[x] = stg[x];
+      }
+      wave_sync();
+    }
+    if (t + stride < p.ntiles) load_raw(t + stride);
+  }
+}
+
+// ------------------------------------------------------------------ FP64 chunk-register
+
+template <int NP>
+constexpr int chunk_ld() { return NP + 1; }  // odd row stride: B-operand reads spread over banks
+
+template <int NP, int WPB>
+constexpr int fwd_f64_chunkreg_lds() { return align16(16 * chunk_ld<NP>() * 8) + 3 * 16 * NP * 8; }
+
+template <int NP, int WPB>
+__device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
+                                                      char* lds) {
+  using Sh = Shape<NP>;
+  static_assert(WPB >= Sh::NCHUNK, "one wave per output chunk");
+  constexpr int KS = Sh::KS64;
+  constexpr int LD = chunk_ld<NP>();
+  constexpr int TILE = 16 * NP;
+  constexpr int NT = WAVE * WPB;
+  constexpr int NLD = (TILE + NT - 1) / NT;  // u words loaded per thread per tile
+  double* us = reinterpret_cast<double*>(lds);
+  double* ostg = reinterpret_cast<double*>(lds + align16(16 * LD * 8));
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int w = tid >> 6;
+  const bool mma = w < Sh::NCHUNK;
+  const int ch = mma ? w : 0;
+  // this wave's A operands, for the whole launch
+  double areg[3][KS];
+#pragma unroll
+  for (int tt = 0; tt < 3; ++tt) {
+    const int T = 3 * ch + tt;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) areg[tt][s] = (mma && T < Sh::MT) ? afrag_f64<NP>(p.D, T, s, lane) : 0.0;
+  }
+  double ur[NLD];
+  auto load_u = [&](uint32_t tt) {
+    const double* __restrict__ src = p.u + (int64_t)tt * TILE;
+    const int cnt = (int)min(16u, p.ncols - tt * 16) * NP;
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int x = tid + NT * q;
+      const double v = src[min(x, cnt - 1)];
+      ur[q] = x < cnt ? v : 0.0;
+    }
+  };
+  uint32_t t = bid;
+  if (t < p.ntiles) load_u(t);
+  for (; t < p.ntiles; t += nblk) {
+    const uint32_t col0 = t * 16;
+    const int cnt = (int)min(16u, p.ncols - col0) * NP;
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int x = tid + NT * q;
+      if (x < TILE) us[(x / NP) * LD + (x % NP)] = ur[q];
+    }
+    __syncthreads();
+    if (t + nblk < p.ntiles) load_u(t + nblk);
+    if (mma) {
+      const uint32_t col = col0 + n;
+      const bool valid = col < p.ncols;
+      const uint32_t k = valid ? col / p.F : 0u;
+      double gk[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) gk[c] = p.G[(int64_t)k * 9 + c];
+      f64x4 acc[3];
+#pragma unroll
+      for (int tt = 0; tt < 3; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int j = 4 * s + g;
+        const double bv = us[n * LD + min(j, NP - 1)];
+        const double b = j < NP ? bv : 0.0;
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt)  // a missing third tile of the last chunk has zero operands
+          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[tt][s], b, acc[tt], 0, 0, 0);
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int tau = 4 * ch + x;
+        const int i = 4 * tau + g;
+        if (tau < Sh::TRIP && i < NP) {
+          const int l0 = 3 * x;
+#pragma unroll
+          for (int bb = 0; bb < 3; ++bb)
+            ostg[bb * TILE + n * NP + i] = gk[bb] * acc[l0 >> 2][l0 & 3] +
+                                           gk[3 + bb] * acc[(l0 + 1) >> 2][(l0 + 1) & 3] +
+                                           gk[6 + bb] * acc[(l0 + 2) >> 2][(l0 + 2) & 3];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+      double* __restrict__ ob = p.out + bb * p.plane + (int64_t)col0 * NP;
+      for (int x = tid; x < cnt; x += NT) ob[x] = ostg[bb * TILE + x];
+    }
+  }
+}
+
+// ------------------------------------------------------------------ split-BF16 staged
+//
+// FP32 words; u is split into hi/lo BF16 in registers after the LDS pick-up, D
+// once when its table is built (or on the fly when the table does not fit).
+// Three BF16 MFMAs per (tile, k-step), cross terms first, FP32 accumulation.
+
+template <int NP>
+constexpr bool bf16_table_fits() { return bf16_table_entries<NP>() * 32 <= 96 * 1024; }
+
+template <int NP, int WPB>
+constexpr int fwd_f32s_staged_lds() {
+  return (bf16_table_fits<NP>() ? 2 * bf16_table_entries<NP>() * 16 : 0) + WPB * 16 * NP * 4;
+}
+
+template <int NP, int WPB>
+__device__ __forceinline__ void fwd_f32s_staged_body(const FwdArgs<float>& p, uint32_t bid, uint32_t nblk,
+                                                     char* lds) {
+  using Sh = Shape<NP>;
+  constexpr bool ALDS = bf16_table_fits<NP>();
+  constexpr int NTE = ALDS ? bf16_table_entries<NP>() : 0;
+  constexpr int TILE = 16 * NP;
+  constexpr int NRAW = (TILE + WAVE - 1) / WAVE;
+  Bf16x8Bits* ahi = reinterpret_cast<Bf16x8Bits*>(lds);
+  Bf16x8Bits* alo = ahi + NTE;
+  float* stg_all = reinterpret_cast<float*>(lds + 2 * NTE * 16);
+  if constexpr (ALDS) {
+    for (int e = threadIdx.x; e < NTE; e += WAVE * WPB) {
+      const int ts = e >> 6;
+      Bf16x8Bits h, l;
+      afrag_bf16<NP>(p.D, ts / Sh::KS16, ts % Sh::KS16, e & 63, h, l);
+      ahi[e] = h;
+      alo[e] = l;
+    }
+    __syncthreads();
+  }
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const uint32_t wave = threadIdx.x >> 6;
+  float* stg = stg_all + wave * TILE;
+  const uint32_t stride = nblk * WPB;
+  uint32_t t = bid * WPB + wave;
+  float raw[NRAW];
+  auto load_raw = [&](uint32_t tt) {
+    const float* __restrict__ src = p.u + (int64_t)tt * TILE;
+    const int cnt = (int)min(16u, p.ncols - tt * 16) * NP;
+#pragma unroll
+    for (int q = 0; q < NRAW; ++q) {
+      const int x = lane + WAVE * q;
+      raw[q] = x < cnt ? src[x] : 0.0f;
+    }
+  };
+  if (t < p.ntiles) load_raw(t);
+  for (; t < p.ntiles; t += stride) {
+    const uint32_t col0 = t * 16;
+    const int cnt = (int)min(16u, p.ncols - col0) * NP;
+#pragma unroll
+    for (int q = 0; q < NRAW; ++q) {
+      const int x = lane + WAVE * q;
+      if (x < TILE) stg[x] = raw[q];
+    }
+    wave_sync();
+    Bf16x8Bits bh[Sh::KS16], bl[Sh::KS16];
+#pragma unroll
+    for (int s = 0; s < Sh::KS16; ++s) {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int j = 32 * s + 8 * g + e;
+        split_bf16(j < NP ? stg[n * NP + j] : 0.0f, bh[s].v[e], bl[s].v[e]);
+      }
+    }
+    const uint32_t col = col0 + n;
+    const bool valid = col < p.ncols;
+    const uint32_t k = valid ? col / p.F : 0u;
+    float gk[9];
+#pragma unroll
+    for (int c = 0; c < 9; ++c) gk[c] = valid ? p.G[(int64_t)k * 9 + c] : 0.0f;
+    wave_sync();
+    f32x4 acc[Sh::MT];
+#pragma unroll
+    for (int T = 0; T < Sh::MT; ++T) acc[T] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < Sh::KS16; ++s) {
+#pragma unroll
+      for (int T = 0; T < Sh::MT; ++T) {
+        Bf16x8Bits ah, al;
+        if constexpr (ALDS) {
+          ah = ahi[(T * Sh::KS16 + s) * WAVE + lane];
+          al = alo[(T * Sh::KS16 + s) * WAVE + lane];
+        } else {
+          afrag_bf16<NP>(p.D, T, s, lane, ah, al);
+        }
+        acc[T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al), as_bf16x8(bh[s]), acc[T], 0, 0, 0);
+        acc[T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bl[s]), acc[T], 0, 0, 0);
+        acc[T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bh[s]), acc[T], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+#pragma unroll
+      for (int tau = 0; tau < Sh::TRIP; ++tau) {
+        const int i = 4 * tau + g;
+        const int s0 = 3 * tau;
+        const float v = gk[bb] * acc[s0 >> 2][s0 & 3] + gk[3 + bb] * acc[(s0 + 1) >> 2][(s0 + 1) & 3] +
+                        gk[6 + bb] * acc[(s0 + 2) >> 2][(s0 + 2) & 3];
+        if (i < NP) stg[n * NP + i] = v;
+      }
+      wave_sync();
+      float* __restrict__ ob = p.out + bb * p.plane + (int64_t)col0 * NP;
+#pragma unroll
+      for (int q = 0; q < NRAW; ++q) {
+        const int x = lane + WAVE * q;
+        if (x < cnt) ob[x] = stg[x];
+      }
+      wave_sync();
+    }
+    if (t + stride < p.ntiles) load_raw(t + stride);
+  }
+}
+
+// ------------------------------------------------------------------ split-BF16 chunk-register
+
+template <int NP, int WPB>
+constexpr int fwd_f32s_chunkreg_lds() { return align16(16 * chunk_ld<NP>() * 4) + 3 * 16 * NP * 4; }
+
+template <int NP, int WPB>
+__device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, uint32_t bid, uint32_t nblk,
+                                                       char* lds) {
+  using Sh = Shape<NP>;
+  static_assert(WPB >= Sh::NCHUNK, "one wave per output chunk");
+  constexpr int KS = Sh::KS16;
+  constexpr int LD = chunk_ld<NP>();
+  constexpr int TILE = 16 * NP;
+  constexpr int NT = WAVE * WPB;
+  constexpr int NLD = (TILE + NT - 1) / NT;
+  float* us = reinterpret_cast<float*>(lds);
+  float* ostg = reinterpret_cast<float*>(lds + align16(16 * LD * 4));
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int w = tid >> 6;
+  const bool mma = w < Sh::NCHUNK;
+  const int ch = mma ? w : 0;
+  Bf16x8Bits ah[3][KS], al[3][KS];
+#pragma unroll
+  for (int tt = 0; tt < 3; ++tt) {
+    const int T = 3 * ch + tt;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      if (mma && T < Sh::MT) {
+        afrag_bf16<NP>(p.D, T, s, lane, ah[tt][s], al[tt][s]);
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) ah[tt][s].v[e] = al[tt][s].v[e] = 0;
+      }
+    }
+  }
+  float ur[NLD];
+  auto load_u = [&](uint32_t tt) {
+    const float* __restrict__ src = p.u + (int64_t)tt * TILE;
+    const int cnt = (int)min(16u, p.ncols - tt * 16) * NP;
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int x = tid + NT * q;
+      const float v = src[min(x, cnt - 1)];
+      ur[q] = x < cnt ? v : 0.0f;
+    }
+  };
+  uint32_t t = bid;
+  if (t < p.ntiles) load_u(t);
+  for (; t < p.ntiles; t += nblk) {
+    const uint32_t col0 = t * 16;
+    const int cnt = (int)min(16u, p.ncols - col0) * NP;
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int x = tid + NT * q;
+      if (x < TILE) us[(x / NP) * LD + (x % NP)] = ur[q];
+    }
+    __syncthreads();
+    if (t + nblk < p.ntiles) load_u(t + nblk);
+    if (mma) {
+      const uint32_t col = col0 + n;
+      const bool valid = col < p.ncols;
+      const uint32_t k = valid ? col / p.F : 0u;
+      float gk[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) gk[c] = p.G[(int64_t)k * 9 + c];
+      f32x4 acc[3];
+#pragma unroll
+      for (int tt = 0; tt < 3; ++tt) acc[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        Bf16x8Bits bh, bl;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int j = 32 * s + 8 * g + e;
+          const float v = us[n * LD + min(j, NP - 1)];
+          split_bf16(j < NP ? v : 0.0f, bh.v[e], bl.v[e]);
+        }
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt) {
+          acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al[tt][s]), as_bf16x8(bh), acc[tt], 0, 0, 0);
+          acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah[tt][s]), as_bf16x8(bl), acc[tt], 0, 0, 0);
+          acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah[tt][s]), as_bf16x8(bh), acc[tt], 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int tau = 4 * ch + x;
+        const int i = 4 * tau + g;
+        if (tau < Sh::TRIP && i < NP) {
+          const int l0 = 3 * x;
+#pragma unroll
+          for (int bb = 0; bb < 3; ++bb)
+            ostg[bb * TILE + n * NP + i] = gk[bb] * acc[l0 >> 2][l0 & 3] +
+                                           gk[3 + bb] * acc[(l0 + 1) >> 2][(l0 + 1) & 3] +
+                                           gk[6 + bb] * acc[(l0 + 2) >> 2][(l0 + 2) & 3];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+      float* __restrict__ ob = p.out + bb * p.plane + (int64_t)col0 * NP;
+      for (int x = tid; x < cnt; x += NT) ob[x] = ostg[bb * TILE + x];
+    }
+  }
+}
+
+}  // namespace dgvol

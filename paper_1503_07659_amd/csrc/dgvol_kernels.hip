@@ -3,425 +3,170 @@
 // Forward:  out_b[i] = sum_a G[3a+b] (D_a u)[i]   for every (element, field) column.
 // Adjoint:  gu = sum_a D_a^T W_a with W_a = sum_b G[3a+b] gout_b;
 //           gG[3a+b] = sum_{f,i} gout_b[i] (D_a u)[i].
-// Definitions, layouts and error behaviour are documented in include/dgvol.h.
-//
-// Design (one wave = 16 columns, persistent grid):
-//  * D is staged once per workgroup in LDS, already permuted into the
-//    per-lane MFMA A-operand order (one conflict-free 8-byte read per lane per
-//    MFMA), when the table fits; otherwise A operands are gathered from D in
-//    global memory (L2-resident).  This is the "precompute into on-chip storage
-//    of a repeatedly fetched operand" of the paper's Section on substitution
-//    rules for precomputation, done by hand.
-//  * u is read once from HBM straight into B-operand registers.
-//  * The stacked product [3Np x Np] . [Np x 16] runs on the FP64 matrix cores
-//    (v_mfma_f64_16x16x4_f64), k = node, in chunks of 3 output tiles.
-//  * The row permutation of dgvol_layout.hpp leaves (D_r u, D_s u, D_t u) of
-//    one node in one lane, so the geometric-factor combine is fused into the
-//    epilogue with no data exchange, and out is written once.
+// Definitions, layouts and error behaviour are documented in include/dgvol.h;
+// the forward data-movement schemes in dgvol_forward.hpp, the adjoint in
+// dgvol_adjoint.hpp, the register layout of the products in dgvol_layout.hpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
+#include <cmath>
 #include <cstdint>
 
 #include "dgvol.h"
+#include "dgvol_adjoint.hpp"
+#include "dgvol_device.hpp"
+#include "dgvol_forward.hpp"
 #include "dgvol_layout.hpp"
 
 namespace dgvol {
 
-typedef double f64x4 __attribute__((ext_vector_type(4)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+constexpr int FWD_WPB = 8;   // waves per workgroup of every forward launch
+constexpr int ADJ_WPB = 4;
 
-constexpr int WAVE = 64;
+// body ids (DG_BODY_STAGED, DG_BODY_CHUNKREG in dgvol.h)
+constexpr int BODY_STAGED = DG_BODY_STAGED;
+constexpr int BODY_CHUNKREG = DG_BODY_CHUNKREG;
 
-// ------------------------------------------------------------------ FP64 A operands
-
-// A operand of output tile T, k-step s, for lane `lane`, read from row-major D.
-// FP64 result rows are 4q + g, so A row m holds slot q = m / 4 of lane group g = m % 4.
 template <int NP>
-__device__ __forceinline__ double afrag_f64(const double* __restrict__ D, int T, int s, int lane) {
-  const int m = lane & 15, kk = lane >> 4;
-  const int q = m >> 2, g = m & 3;
-  const int sigma = 4 * T + q;
-  const int a = slot_dir(sigma), i = slot_node(sigma, g), j = 4 * s + kk;
-  return (sigma < Shape<NP>::SLOTS && i < NP && j < NP) ? D[(a * NP + i) * NP + j] : 0.0;
+constexpr bool f64_staged_ok() { return fwd_f64_staged_lds<NP, FWD_WPB>() <= 160 * 1024; }
+
+template <int NP, int BODY>
+constexpr int f64_lds() {
+  return BODY == BODY_STAGED ? fwd_f64_staged_lds<NP, FWD_WPB>() : fwd_f64_chunkreg_lds<NP, FWD_WPB>();
+}
+template <int NP, int BODY>
+constexpr int f32s_lds() {
+  return BODY == BODY_STAGED ? fwd_f32s_staged_lds<NP, FWD_WPB>() : fwd_f32s_chunkreg_lds<NP, FWD_WPB>();
 }
 
-// A operand of the transposed product (adjoint): tile TJ over output nodes j,
-// k-step sp over the slots of the stacked cotangent W.
-template <int NP>
-__device__ __forceinline__ double afragT_f64(const double* __restrict__ D, int TJ, int sp, int lane) {
-  const int m = lane & 15, kk = lane >> 4;
-  const int j = 16 * TJ + m;
-  const int a = slot_dir(sp), i = slot_node(sp, kk);
-  return (j < NP && i < NP) ? D[(a * NP + i) * NP + j] : 0.0;
+// ------------------------------------------------------------------ single-group kernels
+
+template <int NP, int BODY>
+__global__ __launch_bounds__(WAVE* FWD_WPB) void fwd_f64_kernel(FwdArgs<double> p) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  if constexpr (BODY == BODY_STAGED)
+    fwd_f64_staged_body<NP, FWD_WPB>(p, blockIdx.x, gridDim.x, lds);
+  else
+    fwd_f64_chunkreg_body<NP, FWD_WPB>(p, blockIdx.x, gridDim.x, lds);
 }
 
-template <int NP>
-constexpr int fwd_table_doubles() { return Shape<NP>::MT * Shape<NP>::KS64 * WAVE; }
-
-// Tables up to this size are staged in LDS; larger D is read from global memory.
-constexpr int LDS_TABLE_LIMIT = 96 * 1024;
-
-template <int NP>
-constexpr bool fwd_table_in_lds() { return fwd_table_doubles<NP>() * 8 <= LDS_TABLE_LIMIT; }
-
-template <int NP>
-constexpr bool adj_d_in_lds() { return 3 * NP * NP * 8 <= LDS_TABLE_LIMIT; }
-
-// ------------------------------------------------------------------ forward FP64
-
-template <int NP, int WPB>
-__global__ __launch_bounds__(WAVE* WPB) void fwd_f64_kernel(
-    const double* __restrict__ D, const double* __restrict__ G, const double* __restrict__ u,
-    double* __restrict__ out, uint32_t ncols, uint32_t F, int64_t plane, uint32_t ntiles) {
-  using Sh = Shape<NP>;
-  constexpr bool ALDS = fwd_table_in_lds<NP>();
-  constexpr int NFRAG = ALDS ? fwd_table_doubles<NP>() : 1;
-  __shared__ double afr[NFRAG];
-  const int lane = threadIdx.x & 63;
-  if constexpr (ALDS) {
-    for (int e = threadIdx.x; e < NFRAG; e += WAVE * WPB) {
-      const int ts = e >> 6;
-      afr[e] = afrag_f64<NP>(D, ts / Sh::KS64, ts % Sh::KS64, e & 63);
-    }
-    __syncthreads();
-  }
-  const int n = lane & 15, g = lane >> 4;
-  const uint32_t wave = threadIdx.x >> 6;
-  for (uint32_t t = blockIdx.x * WPB + wave; t < ntiles; t += gridDim.x * WPB) {
-    const uint32_t col = t * 16 + n;
-    const bool valid = col < ncols;
-    const double* __restrict__ uc = u + (int64_t)col * NP;
-    double b[Sh::KS64];
-#pragma unroll
-    for (int s = 0; s < Sh::KS64; ++s) {
-      const int j = 4 * s + g;
-      b[s] = (valid && j < NP) ? uc[j] : 0.0;
-    }
-    const uint32_t k = valid ? col / F : 0u;
-    double gk[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) gk[c] = valid ? G[(int64_t)k * 9 + c] : 0.0;
-    double* __restrict__ oc = out + (int64_t)col * NP;
-#pragma unroll
-    for (int ch = 0; ch < Sh::NCHUNK; ++ch) {
-      f64x4 acc[3];
-#pragma unroll
-      for (int tt = 0; tt < 3; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int s = 0; s < Sh::KS64; ++s) {
-#pragma unroll
-        for (int tt = 0; tt < 3; ++tt) {
-          const int T = 3 * ch + tt;
-          if (T < Sh::MT) {
-            double a;
-            if constexpr (ALDS)
-              a = afr[(T * Sh::KS64 + s) * WAVE + lane];
-            else
-              a = afrag_f64<NP>(D, T, s, lane);
-            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[s], acc[tt], 0, 0, 0);
-          }
-        }
-      }
-#pragma unroll
-      for (int tau = 4 * ch; tau < 4 * ch + 4; ++tau) {
-        if (tau < Sh::TRIP) {
-          double R[3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const int loc = 3 * tau + a - 12 * ch;
-            R[a] = acc[loc >> 2][loc & 3];
-          }
-          const int i = 4 * tau + g;
-          if (valid && i < NP) {
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb)
-              oc[bb * plane + i] = gk[bb] * R[0] + gk[3 + bb] * R[1] + gk[6 + bb] * R[2];
-          }
-        }
-      }
-    }
-  }
+template <int NP, int BODY>
+__global__ __launch_bounds__(WAVE* FWD_WPB) void fwd_f32s_kernel(FwdArgs<float> p) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  if constexpr (BODY == BODY_STAGED)
+    fwd_f32s_staged_body<NP, FWD_WPB>(p, blockIdx.x, gridDim.x, lds);
+  else
+    fwd_f32s_chunkreg_body<NP, FWD_WPB>(p, blockIdx.x, gridDim.x, lds);
 }
 
-// ------------------------------------------------------------------ adjoint FP64
+// ------------------------------------------------------------------ mixed-order batched kernels
 //
-// Tiles are whole elements: E = max(1, 16 / F) elements per tile, split into
-// nsub sub-tiles of 16 columns (nsub > 1 only when F > 16), so the per-element
-// gG sums need no cross-wave reduction.  Per sub-tile and chunk of 4 node
-// triples: recompute R = D u (forward fragments), read gout at the lane's
-// nodes, accumulate gG partials, form W = G^T gout lane-locally, then feed the
-// 12 W slots straight in as the B operand of the transposed product D^T W
-// (the slot order of W is the k order of that product), accumulated over chunks.
+// One persistent launch over up to MAX_GROUPS element groups of different
+// orders.  Workgroups are split between groups on the host in proportion to
+// each group's cost (a static partition: deterministic, no device-side queue,
+// nothing to reset between launches, so the launch can be captured in a
+// graph).  Block b belongs to the group g with wg_begin[g] <= b < wg_begin[g+1]
+// and runs that group's body with its rank and count within the group.
 
-template <int NP, int WPB>
-__global__ __launch_bounds__(WAVE* WPB) void adj_f64_kernel(
-    const double* __restrict__ D, const double* __restrict__ G, const double* __restrict__ u,
-    const double* __restrict__ gout, double* __restrict__ gu, double* __restrict__ gG,
-    uint32_t K, uint32_t F, int64_t plane, uint32_t E, uint32_t nsub, uint32_t ntiles) {
-  using Sh = Shape<NP>;
-  constexpr bool DLDS = adj_d_in_lds<NP>();
-  constexpr int ND = DLDS ? 3 * NP * NP : 1;
-  __shared__ double Dl[ND];
-  __shared__ double red[WPB][16][9];
-  if constexpr (DLDS) {
-    for (int e = threadIdx.x; e < ND; e += WAVE * WPB) Dl[e] = D[e];
-    __syncthreads();
-  }
-  const double* __restrict__ Dsrc = DLDS ? Dl : D;
-  const int lane = threadIdx.x & 63;
-  const int n = lane & 15, g = lane >> 4;
-  const uint32_t wave = threadIdx.x >> 6;
-  for (uint32_t t = blockIdx.x * WPB + wave; t < ntiles; t += gridDim.x * WPB) {
-    const uint32_t k0 = t * E;
-    double P[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) P[c] = 0.0;
-    for (uint32_t sub = 0; sub < nsub; ++sub) {
-      const uint32_t lc = sub * 16 + n;
-      const uint32_t e = (F <= 16) ? lc / F : 0u;
-      const uint32_t f = (F <= 16) ? lc - e * F : lc;
-      const uint32_t k = k0 + e;
-      const bool valid = ((F <= 16) ? (lc < E * F) : (lc < F)) && (k < K);
-      const uint32_t col = valid ? k * F + f : 0u;
-      const double* __restrict__ uc = u + (int64_t)col * NP;
-      double b[Sh::KS64];
-#pragma unroll
-      for (int s = 0; s < Sh::KS64; ++s) {
-        const int j = 4 * s + g;
-        b[s] = (valid && j < NP) ? uc[j] : 0.0;
-      }
-      double gk[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) gk[c] = valid ? G[(int64_t)k * 9 + c] : 0.0;
-      f64x4 accj[Sh::MTJ];
-#pragma unroll
-      for (int tj = 0; tj < Sh::MTJ; ++tj) accj[tj] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int ch = 0; ch < Sh::NCHUNK; ++ch) {
-        f64x4 acc[3];
-#pragma unroll
-        for (int tt = 0; tt < 3; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int s = 0; s < Sh::KS64; ++s) {
-#pragma unroll
-          for (int tt = 0; tt < 3; ++tt) {
-            const int T = 3 * ch + tt;
-            if (T < Sh::MT) {
-              const double a = afrag_f64<NP>(Dsrc, T, s, lane);
-              acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[s], acc[tt], 0, 0, 0);
-            }
-          }
-        }
-        double W[12];
-#pragma unroll
-        for (int x = 0; x < 12; ++x) W[x] = 0.0;
-#pragma unroll
-        for (int tau = 4 * ch; tau < 4 * ch + 4; ++tau) {
-          if (tau < Sh::TRIP) {
-            double R[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              const int loc = 3 * tau + a - 12 * ch;
-              R[a] = acc[loc >> 2][loc & 3];
-            }
-            const int i = 4 * tau + g;
-            const bool inb = valid && i < NP;
-            double go[3];
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb)
-              go[bb] = inb ? gout[bb * plane + (int64_t)col * NP + i] : 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-#pragma unroll
-              for (int bb = 0; bb < 3; ++bb) P[3 * a + bb] += go[bb] * R[a];
-              W[3 * (tau - 4 * ch) + a] = gk[3 * a] * go[0] + gk[3 * a + 1] * go[1] + gk[3 * a + 2] * go[2];
-            }
-          }
-        }
-#pragma unroll
-        for (int sl = 0; sl < 12; ++sl) {
-          const int sp = 12 * ch + sl;
-          if (sp < Sh::SLOTS) {
-#pragma unroll
-            for (int tj = 0; tj < Sh::MTJ; ++tj) {
-              const double a = afragT_f64<NP>(Dsrc, tj, sp, lane);
-              accj[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, W[sl], accj[tj], 0, 0, 0);
-            }
-          }
-        }
-      }
-      double* __restrict__ guc = gu + (int64_t)col * NP;
-#pragma unroll
-      for (int tj = 0; tj < Sh::MTJ; ++tj) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int j = 16 * tj + 4 * q + g;
-          if (valid && j < NP) guc[j] = accj[tj][q];
-        }
-      }
-    }
-    // gG: sum the four lane groups (same column), then the columns of each element.
-#pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      P[c] += __shfl_xor(P[c], 16);
-      P[c] += __shfl_xor(P[c], 32);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (g == 0) {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) red[wave][n][c] = P[c];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (g == 0 && (uint32_t)n < E && k0 + n < K) {
-      const uint32_t lo = (F <= 16) ? n * F : 0u;
-      const uint32_t hi = (F <= 16) ? lo + F : 16u;
-      for (int c = 0; c < 9; ++c) {
-        double s = 0.0;
-        for (uint32_t m = lo; m < hi; ++m) s += red[wave][m][c];
-        gG[(int64_t)(k0 + n) * 9 + c] = s;
-      }
-    }
-  }
-}
+constexpr int MAX_GROUPS = DG_MAX_GROUPS;
 
-// ------------------------------------------------------------------ split-BF16 forward
-
-// Round FP32 to the nearest BF16 (ties to even) in integer arithmetic; returns
-// the FP32 bit pattern with the low 16 bits clear.  NaN stays a quiet NaN.
-__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
-  const uint32_t b = __float_as_uint(x);
-  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu) != 0u) return (b | 0x00400000u) & 0xffff0000u;
-  return (b + 0x7fffu + ((b >> 16) & 1u)) & 0xffff0000u;
-}
-
-// x = hi + lo + O(2^-18 |x|): hi = bf16(x), lo = bf16(x - hi), as BF16 bit patterns.
-__device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
-  const uint32_t h = bf16_rne_bits(x);
-  const float r = x - __uint_as_float(h);  // exact in FP32
-  hi = (uint16_t)(h >> 16);
-  lo = (uint16_t)(bf16_rne_bits(r) >> 16);
-}
-
-struct alignas(16) Bf16x8Bits {
-  uint16_t v[8];
+struct GroupDev {
+  int32_t Np;
+  int32_t body;
+  uint32_t ncols;
+  uint32_t ntiles;
+  int64_t plane;
+  const void* D;
+  const void* G;
+  const void* u;
+  void* out;
 };
 
-__device__ __forceinline__ bf16x8 as_bf16x8(const Bf16x8Bits& x) { return __builtin_bit_cast(bf16x8, x); }
+struct BatchArgs {
+  GroupDev g[MAX_GROUPS];
+  uint32_t wg_begin[MAX_GROUPS + 1];
+  int32_t ngroups;
+  uint32_t F;
+};
 
-// A operand (8 consecutive k per lane) of tile T, k-step s of the BF16 MFMA.
-// BF16 result rows are 4g + q, so A row m holds slot q = m % 4 of lane group g = m / 4.
-template <int NP>
-__device__ __forceinline__ void afrag_bf16(const float* __restrict__ D, int T, int s, int lane,
-                                           Bf16x8Bits& hi, Bf16x8Bits& lo) {
-  const int m = lane & 15, kk = lane >> 4;
-  const int g = m >> 2, q = m & 3;
-  const int sigma = 4 * T + q;
-  const int a = slot_dir(sigma), i = slot_node(sigma, g);
-  const bool row_ok = sigma < Shape<NP>::SLOTS && i < NP;
-#pragma unroll
-  for (int e = 0; e < 8; ++e) {
-    const int j = 32 * s + 8 * kk + e;
-    const float x = (row_ok && j < NP) ? D[(a * NP + i) * NP + j] : 0.0f;
-    split_bf16(x, hi.v[e], lo.v[e]);
-  }
+template <typename T>
+__device__ __forceinline__ FwdArgs<T> group_args(const GroupDev& gd, uint32_t F) {
+  return FwdArgs<T>{static_cast<const T*>(gd.D), static_cast<const T*>(gd.G), static_cast<const T*>(gd.u),
+                    static_cast<T*>(gd.out), gd.ncols, F, gd.plane, gd.ntiles};
 }
 
-template <int NP>
-constexpr int bf16_table_entries() { return Shape<NP>::MT * Shape<NP>::KS16 * WAVE; }
+__device__ __forceinline__ int find_group(const BatchArgs& a) {
+  int gi = 0;
+  while (gi + 1 < a.ngroups && blockIdx.x >= a.wg_begin[gi + 1]) ++gi;
+  return gi;
+}
 
-template <int NP>
-constexpr bool bf16_table_in_lds() { return bf16_table_entries<NP>() * 32 <= LDS_TABLE_LIMIT; }
+#define DGVOL_CASE64(NPV) \
+  case NPV * 2 + BODY_CHUNKREG: fwd_f64_chunkreg_body<NPV, FWD_WPB>(p, bid, nblk, lds); break;
 
-template <int NP, int WPB>
-__global__ __launch_bounds__(WAVE* WPB) void fwd_f32s_kernel(
-    const float* __restrict__ D, const float* __restrict__ G, const float* __restrict__ u,
-    float* __restrict__ out, uint32_t ncols, uint32_t F, int64_t plane, uint32_t ntiles) {
-  using Sh = Shape<NP>;
-  constexpr bool ALDS = bf16_table_in_lds<NP>();
-  constexpr int NT = ALDS ? bf16_table_entries<NP>() : 1;
-  __shared__ Bf16x8Bits ahi[NT];
-  __shared__ Bf16x8Bits alo[NT];
-  const int lane = threadIdx.x & 63;
-  if constexpr (ALDS) {
-    for (int e = threadIdx.x; e < NT; e += WAVE * WPB) {
-      const int ts = e >> 6;
-      Bf16x8Bits h, l;
-      afrag_bf16<NP>(D, ts / Sh::KS16, ts % Sh::KS16, e & 63, h, l);
-      ahi[e] = h;
-      alo[e] = l;
-    }
-    __syncthreads();
+__global__ __launch_bounds__(WAVE* FWD_WPB) void batched_f64_kernel(BatchArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int gi = find_group(a);
+  const GroupDev& gd = a.g[gi];
+  const uint32_t bid = blockIdx.x - a.wg_begin[gi];
+  const uint32_t nblk = a.wg_begin[gi + 1] - a.wg_begin[gi];
+  const FwdArgs<double> p = group_args<double>(gd, a.F);
+  switch (gd.Np * 2 + gd.body) {
+    case 4 * 2 + BODY_STAGED: fwd_f64_staged_body<4, FWD_WPB>(p, bid, nblk, lds); break;
+    case 10 * 2 + BODY_STAGED: fwd_f64_staged_body<10, FWD_WPB>(p, bid, nblk, lds); break;
+    case 20 * 2 + BODY_STAGED: fwd_f64_staged_body<20, FWD_WPB>(p, bid, nblk, lds); break;
+    case 35 * 2 + BODY_STAGED: fwd_f64_staged_body<35, FWD_WPB>(p, bid, nblk, lds); break;
+    case 56 * 2 + BODY_STAGED: fwd_f64_staged_body<56, FWD_WPB>(p, bid, nblk, lds); break;
+    DGVOL_CASE64(4)
+    DGVOL_CASE64(10)
+    DGVOL_CASE64(20)
+    DGVOL_CASE64(35)
+    DGVOL_CASE64(56)
+    DGVOL_CASE64(84)
+    DGVOL_CASE64(120)
+    default: break;
   }
-  const int n = lane & 15, g = lane >> 4;
-  const uint32_t wave = threadIdx.x >> 6;
-  for (uint32_t t = blockIdx.x * WPB + wave; t < ntiles; t += gridDim.x * WPB) {
-    const uint32_t col = t * 16 + n;
-    const bool valid = col < ncols;
-    const float* __restrict__ uc = u + (int64_t)col * NP;
-    Bf16x8Bits bh[Sh::KS16], bl[Sh::KS16];
-#pragma unroll
-    for (int s = 0; s < Sh::KS16; ++s) {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int j = 32 * s + 8 * g + e;
-        const float x = (valid && j < NP) ? uc[j] : 0.0f;
-        split_bf16(x, bh[s].v[e], bl[s].v[e]);
-      }
-    }
-    const uint32_t k = valid ? col / F : 0u;
-    float gk[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) gk[c] = valid ? G[(int64_t)k * 9 + c] : 0.0f;
-    float* __restrict__ oc = out + (int64_t)col * NP;
-#pragma unroll
-    for (int ch = 0; ch < Sh::NCHUNK; ++ch) {
-      f32x4 acc[3];
-#pragma unroll
-      for (int tt = 0; tt < 3; ++tt) acc[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < Sh::KS16; ++s) {
-#pragma unroll
-        for (int tt = 0; tt < 3; ++tt) {
-          const int T = 3 * ch + tt;
-          if (T < Sh::MT) {
-            Bf16x8Bits ah, al;
-            if constexpr (ALDS) {
-              ah = ahi[(T * Sh::KS16 + s) * WAVE + lane];
-              al = alo[(T * Sh::KS16 + s) * WAVE + lane];
-            } else {
-              afrag_bf16<NP>(D, T, s, lane, ah, al);
-            }
-            // small cross terms first, then hi x hi
-            acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al), as_bf16x8(bh[s]), acc[tt], 0, 0, 0);
-            acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bl[s]), acc[tt], 0, 0, 0);
-            acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bh[s]), acc[tt], 0, 0, 0);
-          }
-        }
-      }
-#pragma unroll
-      for (int tau = 4 * ch; tau < 4 * ch + 4; ++tau) {
-        if (tau < Sh::TRIP) {
-          float R[3];
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const int loc = 3 * tau + a - 12 * ch;
-            R[a] = acc[loc >> 2][loc & 3];
-          }
-          const int i = 4 * tau + g;
-          if (valid && i < NP) {
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb)
-              oc[bb * plane + i] = gk[bb] * R[0] + gk[3 + bb] * R[1] + gk[6 + bb] * R[2];
-          }
-        }
-      }
-    }
+}
+#undef DGVOL_CASE64
+
+#define DGVOL_CASE32(NPV)                                                                   \
+  case NPV * 2 + BODY_STAGED: fwd_f32s_staged_body<NPV, FWD_WPB>(p, bid, nblk, lds); break; \
+  case NPV * 2 + BODY_CHUNKREG: fwd_f32s_chunkreg_body<NPV, FWD_WPB>(p, bid, nblk, lds); break;
+
+__global__ __launch_bounds__(WAVE* FWD_WPB) void batched_f32s_kernel(BatchArgs a) {
+  extern __shared__ __attribute__((aligned(16))) char lds[];
+  const int gi = find_group(a);
+  const GroupDev& gd = a.g[gi];
+  const uint32_t bid = blockIdx.x - a.wg_begin[gi];
+  const uint32_t nblk = a.wg_begin[gi + 1] - a.wg_begin[gi];
+  const FwdArgs<float> p = group_args<float>(gd, a.F);
+  switch (gd.Np * 2 + gd.body) {
+    DGVOL_CASE32(4)
+    DGVOL_CASE32(10)
+    DGVOL_CASE32(20)
+    DGVOL_CASE32(35)
+    DGVOL_CASE32(56)
+    DGVOL_CASE32(84)
+    DGVOL_CASE32(120)
+    default: break;
+  }
+}
+#undef DGVOL_CASE32
+
+// ------------------------------------------------------------------ stream calibration
+//
+// Reads n doubles once and writes `copies` scaled copies of them (dst[c*n + i]
+// = (c + 1) * src[i]) with contiguous 8-byte accesses.  With copies = 1 this is
+// a plain copy of known size (the scale of the hardware byte counters); with
+// copies = 3 it moves bytes in the forward kernel's 1 : 3 read : write mix with
+// no other work (the practical streaming ceiling for that mix).
+__global__ __launch_bounds__(256) void stream_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                                     int64_t n, int32_t copies) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double v = src[i];
+    for (int32_t c = 0; c < copies; ++c) dst[c * n + i] = (double)(c + 1) * v;
   }
 }
 
@@ -429,50 +174,144 @@ __global__ __launch_bounds__(WAVE* WPB) void fwd_f32s_kernel(
 
 constexpr int MAX_DEVICES = 64;
 
-// Persistent grid size: resident blocks per CU (occupancy query) x CU count,
-// cached per kernel instance and device.
-template <typename Kern>
-static int resident_blocks(Kern kernel, int block, int* err) {
-  static std::atomic<int> cache[MAX_DEVICES];
+static int current_device(int* err) {
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0) {
     *err = DG_EDEVICE;
-    return 0;
+    return -1;
   }
+  return dev;
+}
+
+static int cu_count(int dev, int* err) {
+  static std::atomic<int> cache[MAX_DEVICES];
   if (dev < MAX_DEVICES) {
     const int c = cache[dev].load(std::memory_order_relaxed);
     if (c > 0) return c;
   }
-  int cus = 0, per_cu = 0;
+  int cus = 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) {
     *err = DG_EDEVICE;
     return 0;
   }
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, 0) != hipSuccess || per_cu <= 0)
+  if (dev < MAX_DEVICES) cache[dev].store(cus, std::memory_order_relaxed);
+  return cus;
+}
+
+// Resident workgroups of `kernel` on the whole device (the persistent grid
+// size).  Kernels that take all their LDS dynamically (dyn_lds >= 0) get their
+// dynamic-LDS limit raised to the full 160 KiB, and are queried with the
+// largest size of the request's class (so a cached count is never too large);
+// kernels with static LDS only (dyn_lds < 0) are queried as they are.  The
+// result is cached per kernel instance, device and class.
+template <typename Kern>
+static int resident_blocks(Kern kernel, int block, int dyn_lds, int* err) {
+  static std::atomic<int> cache[MAX_DEVICES][5];
+  const int dev = current_device(err);
+  if (dev < 0) return 0;
+  const int cls = dyn_lds < 0 ? 4 : dyn_lds <= 40960 ? 0 : dyn_lds <= 81920 ? 1 : dyn_lds <= 122880 ? 2 : 3;
+  if (dev < MAX_DEVICES) {
+    const int c = cache[dev][cls].load(std::memory_order_relaxed);
+    if (c > 0) return c;
+  }
+  const int cus = cu_count(dev, err);
+  if (*err != DG_OK) return 0;
+  int probe = 0;
+  if (dyn_lds >= 0) {
+    // a failure here surfaces as a launch error of a kernel asking for more than the default limit
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                              160 * 1024);
+    probe = cls == 0 ? 40960 : cls == 1 ? 81920 : cls == 2 ? 122880 : 160 * 1024;
+  }
+  int per_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, probe) != hipSuccess || per_cu <= 0)
     per_cu = 1;
   const int total = cus * per_cu;
-  if (dev < MAX_DEVICES) cache[dev].store(total, std::memory_order_relaxed);
+  if (dev < MAX_DEVICES) cache[dev][cls].store(total, std::memory_order_relaxed);
   return total;
 }
 
 static inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
-constexpr int FWD_WPB = 4;
-constexpr int ADJ_WPB = 4;
+// Default body per order: LDS-staged where memory bounds the problem and D
+// fits LDS, chunk-register where the matrix cores bound it.
+static int default_body_f64(int Np) { return Np <= 56 ? BODY_STAGED : BODY_CHUNKREG; }
+static int default_body_f32s(int Np) { return Np <= 84 ? BODY_STAGED : BODY_CHUNKREG; }
+
+static bool body_ok_f64(int Np, int body) {
+  if (body == BODY_CHUNKREG) return true;
+  if (body != BODY_STAGED) return false;
+  switch (Np) {
+    case 4: return f64_staged_ok<4>();
+    case 10: return f64_staged_ok<10>();
+    case 20: return f64_staged_ok<20>();
+    case 35: return f64_staged_ok<35>();
+    case 56: return f64_staged_ok<56>();
+    default: return false;
+  }
+}
+static bool body_ok_f32s(int, int body) { return body == BODY_STAGED || body == BODY_CHUNKREG; }
 
 template <int NP>
-static dg_status launch_fwd_f64(const double* D, const double* G, const double* u, double* out, int64_t K,
-                                int32_t F, hipStream_t stream) {
-  const uint64_t ncols = (uint64_t)K * (uint64_t)F;
-  const uint32_t ntiles = ceil_div(ncols, 16);
-  auto kern = fwd_f64_kernel<NP, FWD_WPB>;
+static int lds_f64(int body) {
+  if constexpr (f64_staged_ok<NP>())
+    return body == BODY_STAGED ? f64_lds<NP, BODY_STAGED>() : f64_lds<NP, BODY_CHUNKREG>();
+  else
+    return f64_lds<NP, BODY_CHUNKREG>();
+}
+template <int NP>
+static int lds_f32s(int body) {
+  return body == BODY_STAGED ? f32s_lds<NP, BODY_STAGED>() : f32s_lds<NP, BODY_CHUNKREG>();
+}
+
+static int lds_bytes(int form, int Np, int body) {
+#define DGVOL_LDS(NPV) \
+  case NPV: return form == DG_FORM_F64 ? lds_f64<NPV>(body) : lds_f32s<NPV>(body);
+  switch (Np) {
+    DGVOL_LDS(4)
+    DGVOL_LDS(10)
+    DGVOL_LDS(20)
+    DGVOL_LDS(35)
+    DGVOL_LDS(56)
+    DGVOL_LDS(84)
+    DGVOL_LDS(120)
+  }
+#undef DGVOL_LDS
+  return 0;
+}
+
+// Tiles one workgroup processes per step of its loop.
+static inline uint32_t tiles_per_block(int body) { return body == BODY_STAGED ? FWD_WPB : 1; }
+
+template <typename Kern, typename Args>
+static dg_status launch_persistent(Kern kern, const Args& args, uint32_t ntiles, int body, int lds,
+                                   hipStream_t stream) {
   int err = DG_OK;
-  const int cap = resident_blocks(kern, WAVE * FWD_WPB, &err);
+  const int cap = resident_blocks(kern, WAVE * FWD_WPB, lds, &err);
   if (err != DG_OK) return err;
-  const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, FWD_WPB), (uint32_t)cap);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * FWD_WPB), 0, stream, D, G, u, out, (uint32_t)ncols,
-                     (uint32_t)F, (int64_t)ncols * NP, ntiles);
+  const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, tiles_per_block(body)), (uint32_t)cap);
+  hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * FWD_WPB), (size_t)lds, stream, args);
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+}
+
+template <int NP>
+static dg_status launch_fwd_f64(const FwdArgs<double>& p, hipStream_t stream) {
+  if constexpr (f64_staged_ok<NP>()) {
+    if (default_body_f64(NP) == BODY_STAGED)
+      return launch_persistent(fwd_f64_kernel<NP, BODY_STAGED>, p, p.ntiles, BODY_STAGED,
+                               f64_lds<NP, BODY_STAGED>(), stream);
+  }
+  return launch_persistent(fwd_f64_kernel<NP, BODY_CHUNKREG>, p, p.ntiles, BODY_CHUNKREG,
+                           f64_lds<NP, BODY_CHUNKREG>(), stream);
+}
+
+template <int NP>
+static dg_status launch_fwd_f32s(const FwdArgs<float>& p, hipStream_t stream) {
+  if (default_body_f32s(NP) == BODY_STAGED)
+    return launch_persistent(fwd_f32s_kernel<NP, BODY_STAGED>, p, p.ntiles, BODY_STAGED,
+                             f32s_lds<NP, BODY_STAGED>(), stream);
+  return launch_persistent(fwd_f32s_kernel<NP, BODY_CHUNKREG>, p, p.ntiles, BODY_CHUNKREG,
+                           f32s_lds<NP, BODY_CHUNKREG>(), stream);
 }
 
 template <int NP>
@@ -481,29 +320,34 @@ static dg_status launch_adj_f64(const double* D, const double* G, const double* 
   const uint32_t E = F <= 16 ? (uint32_t)(16 / F) : 1u;
   const uint32_t nsub = F <= 16 ? 1u : ceil_div((uint64_t)F, 16);
   const uint32_t ntiles = ceil_div((uint64_t)K, E);
-  auto kern = adj_f64_kernel<NP, ADJ_WPB>;
   int err = DG_OK;
-  const int cap = resident_blocks(kern, WAVE * ADJ_WPB, &err);
-  if (err != DG_OK) return err;
-  const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, ADJ_WPB), (uint32_t)cap);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * ADJ_WPB), 0, stream, D, G, u, gout, gu, gG, (uint32_t)K,
-                     (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
+  if (NP <= 56 && F <= 16) {
+    auto kern = adj_f64_staged_kernel<(NP <= 56 ? NP : 56), ADJ_WPB>;
+    const int cap = resident_blocks(kern, WAVE * ADJ_WPB, -1, &err);
+    if (err != DG_OK) return err;
+    const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, ADJ_WPB), (uint32_t)cap);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * ADJ_WPB), 0, stream, D, G, u, gout, gu, gG, (uint32_t)K,
+                       (uint32_t)F, (int64_t)K * F * NP, E, ntiles);
+  } else {
+    auto kern = adj_f64_kernel<NP, ADJ_WPB>;
+    const int cap = resident_blocks(kern, WAVE * ADJ_WPB, -1, &err);
+    if (err != DG_OK) return err;
+    const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, ADJ_WPB), (uint32_t)cap);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * ADJ_WPB), 0, stream, D, G, u, gout, gu, gG, (uint32_t)K,
+                       (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
+  }
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
 
-template <int NP>
-static dg_status launch_fwd_f32s(const float* D, const float* G, const float* u, float* out, int64_t K,
-                                 int32_t F, hipStream_t stream) {
-  const uint64_t ncols = (uint64_t)K * (uint64_t)F;
-  const uint32_t ntiles = ceil_div(ncols, 16);
-  auto kern = fwd_f32s_kernel<NP, FWD_WPB>;
-  int err = DG_OK;
-  const int cap = resident_blocks(kern, WAVE * FWD_WPB, &err);
-  if (err != DG_OK) return err;
-  const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, FWD_WPB), (uint32_t)cap);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * FWD_WPB), 0, stream, D, G, u, out, (uint32_t)ncols,
-                     (uint32_t)F, (int64_t)ncols * NP, ntiles);
-  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+// Roofline estimate of one 16-column tile (seconds), used to split workgroups
+// between groups when the caller gives no measured cost.
+static double tile_cost_estimate(int form, int Np, uint32_t F) {
+  const double word = form == DG_FORM_F64 ? 8.0 : 4.0;
+  const double bytes = 16.0 * word * (4.0 * Np + 9.0 / F);
+  const double flops = 16.0 * Np * (6.0 * Np + 15.0);
+  const double bw = 5.3e12;                                          // measured streaming rate, 1:3 mix
+  const double peak = form == DG_FORM_F64 ? 78.6e12 : 2.5e15 / 3.0;  // three BF16 passes
+  return std::max(bytes / bw, flops / peak);
 }
 
 // ------------------------------------------------------------------ validation
@@ -532,8 +376,9 @@ int32_t dg_abi_version(void) { return DGVOL_ABI_VERSION; }
 const char* dg_strerror(dg_status s) {
   switch (s) {
     case DG_OK: return "success";
-    case DG_EINVAL: return "invalid argument (null or misaligned pointer, K < 0, F < 1, or K*F too large)";
-    case DG_EUNSUPPORTED: return "unsupported node count Np (supported: 4, 10, 20, 35, 56, 84, 120)";
+    case DG_EINVAL:
+      return "invalid argument (null or misaligned pointer, K < 0, F < 1, K*F too large, or a bad group table)";
+    case DG_EUNSUPPORTED: return "unsupported node count Np (supported: 4, 10, 20, 35, 56, 84, 120), form or body";
     case DG_ELAUNCH: return "kernel launch failed";
     case DG_EDEVICE: return "could not query the current HIP device";
     default: return "unknown status";
@@ -547,6 +392,32 @@ int32_t dg_supported_np(int32_t Np) {
   }
 }
 
+int32_t dg_body_available(int32_t form, int32_t Np, int32_t body) {
+  if (!dg_supported_np(Np)) return 0;
+  if (form == DG_FORM_F64) return body_ok_f64(Np, body) ? 1 : 0;
+  if (form == DG_FORM_F32S) return body_ok_f32s(Np, body) ? 1 : 0;
+  return 0;
+}
+
+int32_t dg_default_body(int32_t form, int32_t Np) {
+  if (!dg_supported_np(Np)) return -1;
+  if (form == DG_FORM_F64) return default_body_f64(Np);
+  if (form == DG_FORM_F32S) return default_body_f32s(Np);
+  return -1;
+}
+
+#define DGVOL_DISPATCH(LAUNCH, ...)            \
+  switch (Np) {                                \
+    case 4: return LAUNCH<4>(__VA_ARGS__);     \
+    case 10: return LAUNCH<10>(__VA_ARGS__);   \
+    case 20: return LAUNCH<20>(__VA_ARGS__);   \
+    case 35: return LAUNCH<35>(__VA_ARGS__);   \
+    case 56: return LAUNCH<56>(__VA_ARGS__);   \
+    case 84: return LAUNCH<84>(__VA_ARGS__);   \
+    case 120: return LAUNCH<120>(__VA_ARGS__); \
+  }                                            \
+  return DG_EUNSUPPORTED;
+
 dg_status dg_volume(const double* D, const double* G, const double* u, double* out, int64_t K, int32_t Np,
                     int32_t F, void* stream) {
   bool noop = false;
@@ -554,17 +425,21 @@ dg_status dg_volume(const double* D, const double* G, const double* u, double* o
   if (st != DG_OK || noop) return st;
   if (!D || !G || !u || !out) return DG_EINVAL;
   if (!aligned(D, 8) || !aligned(G, 8) || !aligned(u, 8) || !aligned(out, 8)) return DG_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  switch (Np) {
-    case 4: return launch_fwd_f64<4>(D, G, u, out, K, F, s);
-    case 10: return launch_fwd_f64<10>(D, G, u, out, K, F, s);
-    case 20: return launch_fwd_f64<20>(D, G, u, out, K, F, s);
-    case 35: return launch_fwd_f64<35>(D, G, u, out, K, F, s);
-    case 56: return launch_fwd_f64<56>(D, G, u, out, K, F, s);
-    case 84: return launch_fwd_f64<84>(D, G, u, out, K, F, s);
-    case 120: return launch_fwd_f64<120>(D, G, u, out, K, F, s);
-  }
-  return DG_EUNSUPPORTED;
+  const uint64_t ncols = (uint64_t)K * (uint64_t)F;
+  const FwdArgs<double> p{D, G, u, out, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * Np, ceil_div(ncols, 16)};
+  DGVOL_DISPATCH(launch_fwd_f64, p, (hipStream_t)stream)
+}
+
+dg_status dg_volume_f32s(const float* D, const float* G, const float* u, float* out, int64_t K, int32_t Np,
+                         int32_t F, void* stream) {
+  bool noop = false;
+  const dg_status st = check_common(K, Np, F, &noop);
+  if (st != DG_OK || noop) return st;
+  if (!D || !G || !u || !out) return DG_EINVAL;
+  if (!aligned(D, 4) || !aligned(G, 4) || !aligned(u, 4) || !aligned(out, 4)) return DG_EINVAL;
+  const uint64_t ncols = (uint64_t)K * (uint64_t)F;
+  const FwdArgs<float> p{D, G, u, out, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * Np, ceil_div(ncols, 16)};
+  DGVOL_DISPATCH(launch_fwd_f32s, p, (hipStream_t)stream)
 }
 
 dg_status dg_volume_adjoint(const double* D, const double* G, const double* u, const double* gout, double* gu,
@@ -576,37 +451,90 @@ dg_status dg_volume_adjoint(const double* D, const double* G, const double* u, c
   if (!aligned(D, 8) || !aligned(G, 8) || !aligned(u, 8) || !aligned(gout, 8) || !aligned(gu, 8) ||
       !aligned(gG, 8))
     return DG_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  switch (Np) {
-    case 4: return launch_adj_f64<4>(D, G, u, gout, gu, gG, K, F, s);
-    case 10: return launch_adj_f64<10>(D, G, u, gout, gu, gG, K, F, s);
-    case 20: return launch_adj_f64<20>(D, G, u, gout, gu, gG, K, F, s);
-    case 35: return launch_adj_f64<35>(D, G, u, gout, gu, gG, K, F, s);
-    case 56: return launch_adj_f64<56>(D, G, u, gout, gu, gG, K, F, s);
-    case 84: return launch_adj_f64<84>(D, G, u, gout, gu, gG, K, F, s);
-    case 120: return launch_adj_f64<120>(D, G, u, gout, gu, gG, K, F, s);
-  }
-  return DG_EUNSUPPORTED;
+  DGVOL_DISPATCH(launch_adj_f64, D, G, u, gout, gu, gG, K, F, (hipStream_t)stream)
 }
 
-dg_status dg_volume_f32s(const float* D, const float* G, const float* u, float* out, int64_t K, int32_t Np,
-                         int32_t F, void* stream) {
-  bool noop = false;
-  const dg_status st = check_common(K, Np, F, &noop);
-  if (st != DG_OK || noop) return st;
-  if (!D || !G || !u || !out) return DG_EINVAL;
-  if (!aligned(D, 4) || !aligned(G, 4) || !aligned(u, 4) || !aligned(out, 4)) return DG_EINVAL;
-  hipStream_t s = (hipStream_t)stream;
-  switch (Np) {
-    case 4: return launch_fwd_f32s<4>(D, G, u, out, K, F, s);
-    case 10: return launch_fwd_f32s<10>(D, G, u, out, K, F, s);
-    case 20: return launch_fwd_f32s<20>(D, G, u, out, K, F, s);
-    case 35: return launch_fwd_f32s<35>(D, G, u, out, K, F, s);
-    case 56: return launch_fwd_f32s<56>(D, G, u, out, K, F, s);
-    case 84: return launch_fwd_f32s<84>(D, G, u, out, K, F, s);
-    case 120: return launch_fwd_f32s<120>(D, G, u, out, K, F, s);
+#undef DGVOL_DISPATCH
+
+dg_status dg_volume_batched(const dg_group* groups, int32_t ngroups, int32_t F, int32_t form, void* stream) {
+  if (ngroups < 0 || ngroups > DG_MAX_GROUPS || F < 1) return DG_EINVAL;
+  if (form != DG_FORM_F64 && form != DG_FORM_F32S) return DG_EUNSUPPORTED;
+  if (ngroups > 0 && !groups) return DG_EINVAL;
+  const uintptr_t word = form == DG_FORM_F64 ? 8 : 4;
+  BatchArgs a{};
+  a.F = (uint32_t)F;
+  double cost[DG_MAX_GROUPS];
+  uint32_t max_blocks[DG_MAX_GROUPS];
+  double total_cost = 0.0;
+  int lds = 0;
+  int ng = 0;
+  for (int i = 0; i < ngroups; ++i) {
+    const dg_group& gr = groups[i];
+    bool noop = false;
+    const dg_status st = check_common(gr.K, gr.Np, F, &noop);
+    if (st != DG_OK) return st;
+    if (gr.body != DG_BODY_AUTO && !dg_body_available(form, gr.Np, gr.body)) return DG_EUNSUPPORTED;
+    if (noop) continue;
+    if (!gr.D || !gr.G || !gr.u || !gr.out) return DG_EINVAL;
+    if (!aligned(gr.D, word) || !aligned(gr.G, word) || !aligned(gr.u, word) || !aligned(gr.out, word))
+      return DG_EINVAL;
+    const int body = gr.body != DG_BODY_AUTO
+                         ? gr.body
+                         : (form == DG_FORM_F64 ? default_body_f64(gr.Np) : default_body_f32s(gr.Np));
+    const uint64_t ncols = (uint64_t)gr.K * (uint64_t)F;
+    GroupDev& gd = a.g[ng];
+    gd.Np = gr.Np;
+    gd.body = body;
+    gd.ncols = (uint32_t)ncols;
+    gd.ntiles = ceil_div(ncols, 16);
+    gd.plane = (int64_t)ncols * gr.Np;
+    gd.D = gr.D;
+    gd.G = gr.G;
+    gd.u = gr.u;
+    gd.out = gr.out;
+    const double per_tile = gr.cost > 0.0 ? gr.cost : tile_cost_estimate(form, gr.Np, (uint32_t)F);
+    cost[ng] = per_tile * gd.ntiles;
+    max_blocks[ng] = ceil_div(gd.ntiles, tiles_per_block(body));
+    total_cost += cost[ng];
+    lds = std::max(lds, lds_bytes(form, gr.Np, body));
+    ++ng;
   }
-  return DG_EUNSUPPORTED;
+  if (ng == 0) return DG_OK;
+  a.ngroups = ng;
+  int err = DG_OK;
+  const int cap = form == DG_FORM_F64 ? resident_blocks(batched_f64_kernel, WAVE * FWD_WPB, lds, &err)
+                                      : resident_blocks(batched_f32s_kernel, WAVE * FWD_WPB, lds, &err);
+  if (err != DG_OK) return err;
+  // split the resident workgroups in proportion to cost; every group gets at least one
+  uint32_t begin = 0;
+  for (int i = 0; i < ng; ++i) {
+    a.wg_begin[i] = begin;
+    uint32_t nb = (uint32_t)std::llround((double)cap * cost[i] / total_cost);
+    nb = std::max<uint32_t>(1u, std::min(nb, max_blocks[i]));
+    begin += nb;
+  }
+  for (int i = ng; i <= MAX_GROUPS; ++i) a.wg_begin[i] = begin;
+  if (form == DG_FORM_F64)
+    hipLaunchKernelGGL(batched_f64_kernel, dim3(begin), dim3(WAVE * FWD_WPB), (size_t)lds, (hipStream_t)stream, a);
+  else
+    hipLaunchKernelGGL(batched_f32s_kernel, dim3(begin), dim3(WAVE * FWD_WPB), (size_t)lds, (hipStream_t)stream,
+                       a);
+  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+}
+
+dg_status dg_stream_calibrate(const double* src, double* dst, int64_t n, int32_t copies, void* stream) {
+  if (n < 0 || copies < 1 || copies > 3) return DG_EINVAL;
+  if (n == 0) return DG_OK;
+  if (!src || !dst || !aligned(src, 8) || !aligned(dst, 8)) return DG_EINVAL;
+  int err = DG_OK;
+  const int dev = current_device(&err);
+  if (dev < 0) return err;
+  const int cus = cu_count(dev, &err);
+  if (err != DG_OK) return err;
+  const int64_t want = (n + 255) / 256;
+  const uint32_t grid = (uint32_t)std::min<int64_t>(want, (int64_t)cus * 64);
+  hipLaunchKernelGGL(stream_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, src, dst, n, copies);
+  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
 
 }  // extern "C"

@@ -27,6 +27,20 @@ DG_EDEVICE = -4
 
 SUPPORTED_NP = (4, 10, 20, 35, 56, 84, 120)
 
+FORM_F64 = 0
+FORM_F32S = 1
+BODY_AUTO = -1
+BODY_STAGED = 0
+BODY_CHUNKREG = 1
+MAX_GROUPS = 16
+
+
+class DgGroup(ctypes.Structure):
+    """Mirror of `dg_group` in dgvol.h."""
+    _fields_ = [("Np", ctypes.c_int32), ("body", ctypes.c_int32), ("K", ctypes.c_int64),
+                ("D", ctypes.c_void_p), ("G", ctypes.c_void_p), ("u", ctypes.c_void_p),
+                ("out", ctypes.c_void_p), ("cost", ctypes.c_double)]
+
 _lib = None
 
 
@@ -60,6 +74,14 @@ def load_library(path=None):
     lib.dg_volume_adjoint.restype = I32
     lib.dg_volume_f32s.argtypes = [P, P, P, P, I64, I32, I32, P]
     lib.dg_volume_f32s.restype = I32
+    lib.dg_stream_calibrate.argtypes = [P, P, I64, I32, P]
+    lib.dg_stream_calibrate.restype = I32
+    lib.dg_volume_batched.argtypes = [ctypes.POINTER(DgGroup), I32, I32, I32, P]
+    lib.dg_volume_batched.restype = I32
+    lib.dg_body_available.argtypes = [I32, I32, I32]
+    lib.dg_body_available.restype = I32
+    lib.dg_default_body.argtypes = [I32, I32]
+    lib.dg_default_body.restype = I32
     if path is None:
         _lib = lib
     return lib
@@ -155,6 +177,65 @@ def dg_volume_f32s(D, G, u, out=None):
                                            K, Np, F, _stream_handle(dev))
     _raise_on(st, "dg_volume_f32s")
     return out
+
+
+def dg_volume_batched(groups, form=FORM_F64, outs=None, bodies=None, costs=None):
+    """Forward derivative of several element groups (possibly different orders) in one launch.
+
+    groups: sequence of (D, G, u) tensor triples sharing F and the form's dtype
+    (float64 for FORM_F64, float32 for FORM_F32S).  outs: optional matching
+    output tensors (3, K, F, Np).  bodies: optional per-group body ids
+    (BODY_AUTO, BODY_STAGED, BODY_CHUNKREG).  costs: optional measured cost of
+    one 16-column tile per group (sets the split of workgroups).  Returns outs.
+    """
+    if len(groups) > MAX_GROUPS:
+        raise ValueError(f"at most {MAX_GROUPS} groups per launch")
+    dtype = torch.float64 if form == FORM_F64 else torch.float32
+    if not groups:
+        return []
+    F = groups[0][2].shape[1] if groups[0][2].dim() == 3 else None
+    dev = groups[0][2].device
+    arr = (DgGroup * max(1, len(groups)))()
+    res = []
+    for gi, (D, G, u) in enumerate(groups):
+        K, Fg, Np = _sizes(u, D)
+        if Fg != F:
+            raise ValueError("all groups of a batch share F")
+        _check_tensor("u", u, dtype, (K, F, Np), dev)
+        _check_tensor("D", D, dtype, (3, Np, Np), dev)
+        _check_tensor("G", G, dtype, (K, 9), dev)
+        out = outs[gi] if outs is not None else torch.empty((3, K, F, Np), dtype=dtype, device=dev)
+        _check_tensor("out", out, dtype, (3, K, F, Np), dev)
+        res.append(out)
+        arr[gi].Np = Np
+        arr[gi].body = BODY_AUTO if bodies is None else int(bodies[gi])
+        arr[gi].K = K
+        arr[gi].D, arr[gi].G, arr[gi].u, arr[gi].out = D.data_ptr(), G.data_ptr(), u.data_ptr(), out.data_ptr()
+        arr[gi].cost = 0.0 if costs is None else float(costs[gi])
+    with torch.cuda.device(dev):
+        st = load_library().dg_volume_batched(arr, len(groups), int(F), int(form), _stream_handle(dev))
+    _raise_on(st, "dg_volume_batched")
+    return res
+
+
+def body_available(form, Np, body):
+    return bool(load_library().dg_body_available(int(form), int(Np), int(body)))
+
+
+def default_body(form, Np):
+    return int(load_library().dg_default_body(int(form), int(Np)))
+
+
+def dg_stream_calibrate(src, dst, copies):
+    """Bandwidth calibration: dst[c*n + i] = (c + 1) * src[i] for c < copies (1..3); FP64."""
+    n = src.numel()
+    dev = src.device
+    _check_tensor("src", src, torch.float64, (n,))
+    _check_tensor("dst", dst, torch.float64, (copies * n,), dev)
+    with torch.cuda.device(dev):
+        st = load_library().dg_stream_calibrate(src.data_ptr(), dst.data_ptr(), n, copies, _stream_handle(dev))
+    _raise_on(st, "dg_stream_calibrate")
+    return dst
 
 
 class DGVolume(torch.autograd.Function):

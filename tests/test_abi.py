@@ -118,3 +118,44 @@ def test_library_geometric_factors():
     bad[5, 3] = bad[5, 0]
     with pytest.raises(ValueError):
         setup_host.geometric_factors(bad)
+
+
+def _groups(n, **kw):
+    arr = (dgvol.DgGroup * max(n, 1))()
+    for i in range(n):
+        arr[i].Np, arr[i].body, arr[i].K = kw.get("Np", 35), kw.get("body", -1), kw.get("K", 10)
+        arr[i].D = arr[i].G = arr[i].u = arr[i].out = kw.get("ptr", FAKE)
+        arr[i].cost = 0.0
+    return arr
+
+
+def test_batched_validation(lib):
+    f = lib.dg_volume_batched
+    assert ctypes.sizeof(dgvol.DgGroup) == 56
+    assert f(_groups(0), 0, 3, dgvol.FORM_F64, None) == dgvol.DG_OK
+    assert f(_groups(3, K=0), 3, 3, dgvol.FORM_F64, None) == dgvol.DG_OK        # all empty: no-op
+    assert f(_groups(17), 17, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL       # too many groups
+    assert f(_groups(2), -1, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL
+    assert f(_groups(2), 2, 0, dgvol.FORM_F64, None) == dgvol.DG_EINVAL         # F < 1
+    assert f(_groups(2), 2, 3, 7, None) == dgvol.DG_EUNSUPPORTED               # unknown form
+    assert f(_groups(2, Np=36), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EUNSUPPORTED
+    assert f(_groups(2, K=-1), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL
+    assert f(_groups(2, ptr=None), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL
+    assert f(_groups(2, ptr=FAKE + 4), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL  # misaligned double
+    assert f(_groups(2, body=5), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EUNSUPPORTED
+    # the staged FP64 body needs D in LDS: not available for the two largest orders
+    assert f(_groups(1, Np=120, body=0, K=0), 1, 3, dgvol.FORM_F64, None) == dgvol.DG_EUNSUPPORTED
+    assert f(None, 1, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL
+
+
+def test_bodies(lib):
+    for Np in (4, 10, 20, 35, 56, 84, 120):
+        assert lib.dg_body_available(dgvol.FORM_F64, Np, dgvol.BODY_CHUNKREG) == 1
+        assert lib.dg_body_available(dgvol.FORM_F32S, Np, dgvol.BODY_STAGED) == 1
+        assert lib.dg_body_available(dgvol.FORM_F32S, Np, dgvol.BODY_CHUNKREG) == 1
+        for form in (dgvol.FORM_F64, dgvol.FORM_F32S):
+            d = lib.dg_default_body(form, Np)
+            assert d in (0, 1) and lib.dg_body_available(form, Np, d) == 1
+    assert [lib.dg_body_available(dgvol.FORM_F64, n, dgvol.BODY_STAGED) for n in (35, 56, 84, 120)] == [1, 1, 0, 0]
+    assert lib.dg_default_body(dgvol.FORM_F64, 36) == -1
+    assert lib.dg_body_available(5, 35, 0) == 0

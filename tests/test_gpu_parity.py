@@ -269,3 +269,81 @@ def test_f32s_orders(N):
     got = host(dgvol.dg_volume_f32s(dev(D.astype(np.float32)), dev(G.astype(np.float32)),
                                     dev(u.astype(np.float32)))).astype(np.float64)
     _check_f32s(D, G, u, got)
+
+
+# ------------------------------------------------------------------ bandwidth calibration kernel
+
+def test_stream_calibrate():
+    _say("stream calibrate")
+    n = 100003
+    src = torch.arange(n, dtype=torch.float64, device="cuda") * 0.5 - 7.0
+    for copies in (1, 2, 3):
+        dst = torch.full((copies * n,), float("nan"), dtype=torch.float64, device="cuda")
+        dgvol.dg_stream_calibrate(src, dst, copies)
+        want = torch.cat([(c + 1) * src for c in range(copies)])
+        assert torch.equal(dst, want)
+
+
+# ------------------------------------------------------------------ mixed-order batched launch
+
+def _mixed_case(sizes, F, form, seed):
+    D, G, u = {}, {}, {}
+    for N, K in sizes.items():
+        D[N] = oracle.derivative_matrices(N)
+        G[N] = oracle.geometric_factors(synth.tet_vertices(K, seed + N))
+        u[N] = synth.fields(K, F, oracle.num_nodes(N), seed + 100 + N, "normal")
+    return D, G, u
+
+
+@pytest.mark.parametrize("form", [dgvol.FORM_F64, dgvol.FORM_F32S])
+def test_batched_matches_single_and_oracle(form):
+    """Orders 1..7 with uneven element counts in one launch: each group is bitwise equal to the
+    single-group call (same body) and meets the parity bar against the oracle."""
+    sizes = {1: 1000, 2: 37, 3: 513, 4: 129, 5: 300, 6: 71, 7: 250}
+    F = 3
+    _say(f"batched form={form} sizes={sizes}")
+    D, G, u = _mixed_case(sizes, F, form, 4000)
+    cast = (lambda x: x) if form == dgvol.FORM_F64 else (lambda x: x.astype(np.float32))
+    trip = [(dev(cast(D[N])), dev(cast(G[N])), dev(cast(u[N]))) for N in sizes]
+    outs = dgvol.dg_volume_batched(trip, form=form)
+    single = dgvol.dg_volume if form == dgvol.FORM_F64 else dgvol.dg_volume_f32s
+    for (N, K), (Dd, Gd, ud), o in zip(sizes.items(), trip, outs):
+        got = host(o)
+        assert np.array_equal(got, host(single(Dd, Gd, ud))), f"order {N}: batched != single"
+        if form == dgvol.FORM_F64:
+            check_planes(got, oracle.volume(D[N], G[N], u[N]), forward_cond(D[N], G[N], u[N]))
+        else:
+            _check_f32s(D[N], G[N], u[N], got.astype(np.float64))
+
+
+@pytest.mark.parametrize("form", [dgvol.FORM_F64, dgvol.FORM_F32S])
+def test_batched_every_body(form):
+    """Every available body of every order gives the oracle's result (and equal results across
+    bodies up to the parity bar)."""
+    sizes = {N: 97 for N in range(1, 8)}
+    F = 2
+    _say(f"batched bodies form={form}")
+    D, G, u = _mixed_case(sizes, F, form, 4100)
+    cast = (lambda x: x) if form == dgvol.FORM_F64 else (lambda x: x.astype(np.float32))
+    for body in (dgvol.BODY_STAGED, dgvol.BODY_CHUNKREG):
+        Ns = [N for N in sizes if dgvol.body_available(form, oracle.num_nodes(N), body)]
+        trip = [(dev(cast(D[N])), dev(cast(G[N])), dev(cast(u[N]))) for N in Ns]
+        outs = dgvol.dg_volume_batched(trip, form=form, bodies=[body] * len(Ns))
+        for N, o in zip(Ns, outs):
+            got = host(o)
+            if form == dgvol.FORM_F64:
+                check_planes(got, oracle.volume(D[N], G[N], u[N]), forward_cond(D[N], G[N], u[N]))
+            else:
+                _check_f32s(D[N], G[N], u[N], got.astype(np.float64))
+
+
+def test_batched_skips_empty_groups_and_weights():
+    F = 1
+    _say("batched empty groups and weights")
+    D, G, u = _mixed_case({2: 50, 5: 60}, F, dgvol.FORM_F64, 4200)
+    empty = (dev(oracle.derivative_matrices(3)), torch.zeros((0, 9), dtype=torch.float64, device="cuda"),
+             torch.zeros((0, F, 20), dtype=torch.float64, device="cuda"))
+    trip = [(dev(D[2]), dev(G[2]), dev(u[2])), empty, (dev(D[5]), dev(G[5]), dev(u[5]))]
+    outs = dgvol.dg_volume_batched(trip, costs=[1.0, 0.0, 50.0])
+    for N, o in ((2, outs[0]), (5, outs[2])):
+        check_planes(host(o), oracle.volume(D[N], G[N], u[N]), forward_cond(D[N], G[N], u[N]))
