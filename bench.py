@@ -128,6 +128,51 @@ def cpu_baseline(D, G, u, min_seconds=10.0, max_reps=1000):
             "sample": f"first {K} of {WORKLOAD['K']} elements (order 4, F=5), {reps} pass(es) in {el:.1f} s"}
 
 
+def mixed_orders(torch, dev):
+    """Orders 1..7 in one persistent launch (group sizes round(2^U(10,18)), seed 3004), F = 3,
+    FP64 and split-BF16: eager default launch, autotuned launch, graph replay of the tuned
+    launch, and one launch per order for comparison; roofline = sum over groups of
+    max(bytes / HBM peak, flops / matrix peak)."""
+    from paper_1503_07659_amd import autotune, dgvol, setup_host, synth
+    from paper_1503_07659_amd.graph import CapturedLaunch
+    F = 3
+    sizes = synth.mixed_order_sizes()
+    res = {"group_sizes": {str(N): K for N, K in sizes.items()}, "F": F}
+    host = {}
+    for N, K in sizes.items():
+        Np = setup_host.NODE_COUNTS[N]
+        host[N] = (setup_host.reference_matrices(N),
+                   setup_host.geometric_factors(synth.tet_vertices(K, synth.mesh_seed(4) + 10 * N)),
+                   synth.fields(K, F, Np, synth.field_seed(4) + 10 * N, "normal"))
+    dofs = sum(K * F * setup_host.NODE_COUNTS[N] for N, K in sizes.items())
+    for form, name, dt, word in ((dgvol.FORM_F64, "fp64", torch.float64, 8),
+                                 (dgvol.FORM_F32S, "f32s", torch.float32, 4)):
+        trip = [tuple(torch.from_numpy(x).to(device=dev, dtype=dt) for x in host[N]) for N in sizes]
+        outs = [torch.empty((3,) + tuple(t[2].shape), dtype=dt, device=dev) for t in trip]
+        ms_auto, _ = time_launches(lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs), 20, 3, torch)
+        bodies, costs = autotune.plan(trip, form)
+        tuned = lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs, bodies=bodies, costs=costs)  # noqa: E731
+        ms_tuned, _ = time_launches(tuned, 20, 3, torch)
+        cap = CapturedLaunch(tuned)
+        ms_graph, _ = time_launches(cap.replay, 20, 3, torch)
+        single = dgvol.dg_volume if form == dgvol.FORM_F64 else dgvol.dg_volume_f32s
+        ms_sep, _ = time_launches(lambda: [single(D, G, u, out=o) for (D, G, u), o in zip(trip, outs)], 20, 3, torch)
+        peak = FP64_PEAK_TFS * 1e12 if form == dgvol.FORM_F64 else 2.5e15 / 3
+        roof = 0.0
+        for N, K in sizes.items():
+            Np = setup_host.NODE_COUNTS[N]
+            roof += max(K * fwd_bytes_per_element(F, Np, word) / (HBM_PEAK_GBS * 1e9),
+                        K * fwd_flops_per_element(F, Np) / peak)
+        res[name] = {"GDOF/s": round(dofs / (ms_graph * 1e-3) / 1e9, 3), "graph_replay_ms": round(ms_graph, 5),
+                     "tuned_ms": round(ms_tuned, 5), "default_ms": round(ms_auto, 5),
+                     "one_launch_per_order_ms": round(ms_sep, 5), "roofline_ms": round(roof * 1e3, 5),
+                     "frac_of_roofline": round(roof * 1e3 / ms_graph, 4),
+                     "bodies": {str(N): int(b) for N, b in zip(sizes, bodies)}}
+        del trip, outs, cap
+        torch.cuda.empty_cache()
+    return res
+
+
 def workload_inputs():
     from paper_1503_07659_amd import setup_host, synth
     N, K, F = WORKLOAD["N"], WORKLOAD["K"], WORKLOAD["F"]
@@ -332,6 +377,9 @@ def main():
             "adjoint_GDOF/s": round(d5 / (msa * 1e-3) / 1e9, 3), "adjoint_kernel_ms": round(ka, 5),
             "adjoint_fp64_frac": round(fl_a / (ka * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
             "adjoint_hbm_frac": round(K5 * adj_bytes_per_element(F5, Np5) / (ka * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        del D5, G5, u5, o5, g5, gu5, gG5
+        torch.cuda.empty_cache()
+        forms["mixed_orders1to7_F3"] = mixed_orders(torch, dev)
         rec["forms"] = forms
 
     if not args.no_cpu:

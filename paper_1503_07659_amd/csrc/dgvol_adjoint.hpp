@@ -167,13 +167,20 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_kernel(
 // runs; gout is read at each lane's own nodes, one chunk ahead of its use.
 template <int NP>
 constexpr int adj_table_rows() {
-  // rows read by the transposed product may run past the forward table by up to
-  // 4 * MTJ + 3 - KS rows (output nodes j >= Np, whose results are discarded)
-  return Shape<NP>::MT * Shape<NP>::KS64 + 4 * Shape<NP>::MTJ + 4;
+  // the transposed product reads rows up to ((SLOTS - 1) / 4) KS + 4 MTJ - 1 (rows past
+  // the forward table belong to output nodes j >= Np, whose results are discarded)
+  using Sh = Shape<NP>;
+  constexpr int need = ((Sh::SLOTS - 1) / 4) * Sh::KS64 + 4 * Sh::MTJ;
+  return need > Sh::MT * Sh::KS64 ? need : Sh::MT * Sh::KS64;
 }
 
 template <int NP, int WPB>
-__global__ __launch_bounds__(WAVE* WPB) void adj_f64_staged_kernel(
+constexpr int adj_staged_lds() {
+  return adj_table_rows<NP>() * WAVE * 8 + WPB * 16 * (NP + 1) * 8 + 2 * WPB * 16 * 9 * 8;
+}
+
+template <int NP, int WPB>
+__global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8))) void adj_f64_staged_kernel(
     const double* __restrict__ D, const double* __restrict__ G, const double* __restrict__ u,
     const double* __restrict__ gout, double* __restrict__ gu, double* __restrict__ gG, uint32_t K, uint32_t F,
     int64_t plane, uint32_t E, uint32_t ntiles) {
@@ -181,11 +188,14 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_staged_kernel(
   constexpr int KS = Sh::KS64;
   constexpr int NFRAG = fwd_table_doubles<NP>();
   constexpr int NTAB = adj_table_rows<NP>() * WAVE;
+  constexpr int LD = NP + 1;  // odd row stride of the tile buffer: B-operand reads spread over banks
   constexpr int TILE = 16 * NP;
   constexpr int NRAW = (TILE + WAVE - 1) / WAVE;
   __shared__ double afr[NTAB];
-  __shared__ double stg_all[WPB * TILE];
+  __shared__ double stg_all[WPB * 16 * LD];
   __shared__ double red_all[WPB * 16 * 9];
+  __shared__ double gks_all[WPB * 16 * 9];
+  static_assert(adj_staged_lds<NP, WPB>() <= 160 * 1024, "LDS budget");
   for (int e = threadIdx.x; e < NTAB; e += WAVE * WPB) {
     const int row = e >> 6, l = e & 63;
     afr[row * WAVE + tswz(l, row % KS)] = e < NFRAG ? afrag_f64<NP>(D, row / KS, row % KS, l) : 0.0;
@@ -194,8 +204,9 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_staged_kernel(
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
   const uint32_t wave = threadIdx.x >> 6;
-  double* stg = stg_all + wave * TILE;
+  double* stg = stg_all + wave * 16 * LD;
   double* red = red_all + wave * 16 * 9;
+  double* gks = gks_all + wave * 16 * 9;  // geometric factors of the wave's 16 columns
   // per-lane LDS offsets: forward rows by s & 3, transposed rows by sp & 3
   int fo[4], tb[4];
 #pragma unroll
@@ -203,7 +214,6 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_staged_kernel(
     fo[r] = tswz(lane, r);
     tb[r] = (n >> 2) * WAVE + ((16 * (n & 3) + 4 * r + g) ^ ((n >> 2) << 2));
   }
-  // B-operand pick-up offsets into the tile buffer (clamped; masked by bmask)
   const uint32_t stride = gridDim.x * WPB;
   uint32_t t = blockIdx.x * WPB + wave;
   double raw[NRAW];
@@ -228,23 +238,17 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_staged_kernel(
 #pragma unroll
     for (int q = 0; q < NRAW; ++q) {
       const int x = lane + WAVE * q;
-      if (NRAW * WAVE == TILE || x < TILE) stg[x] = raw[q];
-    }
-    wave_sync();
-    double b[KS];
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const int j = 4 * s + g;
-      const double v = stg[n * NP + min(j, NP - 1)];
-      b[s] = j < NP ? v : 0.0;
+      if (NRAW * WAVE == TILE || x < TILE) stg[(x / NP) * LD + (x % NP)] = raw[q];
     }
     wave_sync();
     const bool valid = (uint32_t)n < ncolt;
     const uint32_t e = valid ? (uint32_t)n / F : 0u;
     const uint32_t col = col0 + (valid ? n : 0);
-    double gk[9];
+    if (g == 0) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) gk[c] = G[(int64_t)(k0 + e) * 9 + c];
+      for (int c = 0; c < 9; ++c) gks[n * 9 + c] = G[(int64_t)(k0 + e) * 9 + c];
+    }
+    wave_sync();
     const double* __restrict__ goc = gout + (int64_t)col * NP;
     f64x4 accj[Sh::MTJ];
 #pragma unroll
@@ -273,11 +277,14 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_staged_kernel(
       for (int tt = 0; tt < 3; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
+        const int j = 4 * s + g;
+        const double bv = stg[n * LD + min(j, NP - 1)];
+        const double b = j < NP ? bv : 0.0;
 #pragma unroll
         for (int tt = 0; tt < 3; ++tt) {
           const int T = 3 * ch + tt;
           if (T < Sh::MT)
-            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[(T * KS + s) * WAVE + fo[s & 3]], b[s], acc[tt], 0, 0, 0);
+            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[(T * KS + s) * WAVE + fo[s & 3]], b, acc[tt], 0, 0, 0);
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -294,7 +301,8 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_staged_kernel(
             const double R = acc[loc >> 2][loc & 3];
 #pragma unroll
             for (int bb = 0; bb < 3; ++bb) P[3 * a + bb] += go[x][bb] * R;
-            W[loc] = gk[3 * a] * go[x][0] + gk[3 * a + 1] * go[x][1] + gk[3 * a + 2] * go[x][2];
+            W[loc] = gks[n * 9 + 3 * a] * go[x][0] + gks[n * 9 + 3 * a + 1] * go[x][1] +
+                     gks[n * 9 + 3 * a + 2] * go[x][2];
           }
         }
       }
@@ -310,13 +318,14 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_staged_kernel(
         }
       }
     }
-    // gu through the tile buffer
+    // gu through the tile buffer (after every lane's last B-operand read)
+    wave_sync();
 #pragma unroll
     for (int tj = 0; tj < Sh::MTJ; ++tj) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j = 16 * tj + 4 * q + g;
-        if (16 * tj + 16 <= NP || j < NP) stg[n * NP + min(j, NP - 1)] = accj[tj][q];
+        if (16 * tj + 16 <= NP || j < NP) stg[n * LD + min(j, NP - 1)] = accj[tj][q];
       }
     }
     wave_sync();
@@ -324,7 +333,7 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_staged_kernel(
 #pragma unroll
     for (int q = 0; q < NRAW; ++q) {
       const int x = lane + WAVE * q;
-      if (x < cnt) gdst[x] = stg[x];
+      if (x < cnt) gdst[x] = stg[(x / NP) * LD + (x % NP)];
     }
     // gG: four lane groups, then the F columns of each element, in a fixed order
 #pragma unroll

@@ -22,7 +22,7 @@
 namespace dgvol {
 
 constexpr int FWD_WPB = 8;   // waves per workgroup of every forward launch
-constexpr int ADJ_WPB = 4;
+constexpr int ADJ_WPB = 8;
 
 // body ids (DG_BODY_STAGED, DG_BODY_CHUNKREG in dgvol.h)
 constexpr int BODY_STAGED = DG_BODY_STAGED;

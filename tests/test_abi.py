@@ -159,3 +159,21 @@ def test_bodies(lib):
     assert [lib.dg_body_available(dgvol.FORM_F64, n, dgvol.BODY_STAGED) for n in (35, 56, 84, 120)] == [1, 1, 0, 0]
     assert lib.dg_default_body(dgvol.FORM_F64, 36) == -1
     assert lib.dg_body_available(5, 35, 0) == 0
+
+
+def test_autotune_cache_io(tmp_path, monkeypatch):
+    """Cache file handling needs no GPU: corrupt or foreign content is ignored."""
+    from paper_1503_07659_amd import autotune
+    p = tmp_path / "c.json"
+    monkeypatch.setenv("DGVOL_AUTOTUNE_CACHE", str(p))
+    assert autotune.load_cache() == {}
+    p.write_text("[1, 2")
+    assert autotune.load_cache() == {}
+    p.write_text("[1, 2]")
+    assert autotune.load_cache() == {}
+    autotune.save_cache({"gfx950/abi1": {"f64/Np35/F3": {"body": 0, "tile_cost_s": 1e-7}}})
+    assert autotune.load_cache()["gfx950/abi1"]["f64/Np35/F3"]["body"] == 0
+    assert autotune._valid_entry({"body": 1, "tile_cost_s": 2e-7})
+    assert not autotune._valid_entry({"body": 1, "tile_cost_s": -1})
+    assert not autotune._valid_entry({"body": "x", "tile_cost_s": 1})
+    assert autotune.entry_key(1, 120, 3) == "f32s/Np120/F3"

@@ -347,3 +347,45 @@ def test_batched_skips_empty_groups_and_weights():
     outs = dgvol.dg_volume_batched(trip, costs=[1.0, 0.0, 50.0])
     for N, o in ((2, outs[0]), (5, outs[2])):
         check_planes(host(o), oracle.volume(D[N], G[N], u[N]), forward_cond(D[N], G[N], u[N]))
+
+
+# ------------------------------------------------------------------ graph capture and autotuning
+
+def test_graph_replay_matches_eager():
+    """The batched launch captured in a graph replays bitwise equal to the eager launch, every
+    replay, with eager work in between."""
+    from paper_1503_07659_amd.graph import CapturedLaunch
+    sizes = {1: 700, 3: 250, 5: 90, 7: 120}
+    F = 3
+    _say("graph replay")
+    D, G, u = _mixed_case(sizes, F, dgvol.FORM_F64, 4300)
+    trip = [(dev(D[N]), dev(G[N]), dev(u[N])) for N in sizes]
+    eager = [host(o).copy() for o in dgvol.dg_volume_batched(trip)]
+    outs = [torch.full((3,) + tuple(t[2].shape), float("nan"), dtype=torch.float64, device="cuda") for t in trip]
+    cap = CapturedLaunch(lambda: dgvol.dg_volume_batched(trip, outs=outs))
+    for rep in range(3):
+        for o in outs:
+            o.fill_(float("nan"))
+        torch.cuda.synchronize()
+        cap.replay()
+        torch.cuda.synchronize()
+        for N, o, e in zip(sizes, outs, eager):
+            assert np.array_equal(host(o), e), f"replay {rep}, order {N}"
+        dgvol.dg_volume_batched(trip)  # eager work between replays
+        torch.cuda.synchronize()
+
+
+def test_autotuner_cache_and_tuned_launch(tmp_path, monkeypatch):
+    from paper_1503_07659_amd import autotune
+    monkeypatch.setenv("DGVOL_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
+    _say("autotune")
+    (tmp_path / "cache.json").write_text("{not json")  # a corrupt cache is ignored and rewritten
+    e = autotune.tune(dgvol.FORM_F64, 35, 3, target_bytes=32 << 20, reps=3)
+    assert e["body"] in (0, 1) and e["tile_cost_s"] > 0
+    assert autotune.lookup(dgvol.FORM_F64, 35, 3, tune_missing=False)["body"] == e["body"]
+    sizes = {2: 300, 4: 200, 6: 50}
+    D, G, u = _mixed_case(sizes, 3, dgvol.FORM_F64, 4400)
+    trip = [(dev(D[N]), dev(G[N]), dev(u[N])) for N in sizes]
+    outs = autotune.volume_batched_tuned(trip)
+    for N, o in zip(sizes, outs):
+        check_planes(host(o), oracle.volume(D[N], G[N], u[N]), forward_cond(D[N], G[N], u[N]))
