@@ -14,9 +14,10 @@
 //    16-column tiles and moves u in and each output plane out through one LDS
 //    buffer of 16 x Np words, so all global accesses are contiguous runs.
 //  * chunk-register (matrix-core-bound orders, D too large for LDS): the
-//    workgroup shares one 16-column tile; wave w keeps the A operands of output
-//    chunk w (3 tiles) in registers for the whole launch; u is staged once per
-//    tile in LDS and read by all waves; the output planes are assembled in LDS.
+//    workgroup shares a run of 16-column tiles per iteration; wave w keeps the
+//    A operands of output chunk w (3 tiles) in registers for the whole launch;
+//    u and the geometric factors are staged per iteration in LDS and read by
+//    all waves; the output planes are assembled in LDS.
 // Each body takes its block index and block count explicitly and carves its
 // LDS from one dynamic buffer, so the same code serves every launch shape.
 #pragma once
@@ -143,8 +144,94 @@ __device__ __forceinline__ void fwd_f64_staged_body(const FwdArgs<double>& p, ui
 template <int NP>
 constexpr int chunk_ld() { return NP + 1; }  // odd row stride: B-operand reads spread over banks
 
+// Column tiles the workgroup shares per iteration of the chunk-register bodies:
+// more tiles per iteration means fewer barriers per byte and more bytes in flight,
+// at the cost of prefetch registers (FP64 at Np = 120 has none to spare).
+template <int NP, int WORD>
+constexpr int chunk_tpw() { return WORD == 4 ? 4 : (NP >= 120 ? 1 : 2); }
+
+template <int NP, int WORD>
+constexpr int chunk_lds() {
+  constexpr int TPW = chunk_tpw<NP, WORD>();
+  return align16(TPW * 16 * chunk_ld<NP>() * WORD) + align16(3 * TPW * 16 * NP * WORD) + TPW * 16 * 9 * WORD;
+}
+
 template <int NP, int WPB>
-constexpr int fwd_f64_chunkreg_lds() { return align16(16 * chunk_ld<NP>() * 8) + 3 * 16 * NP * 8; }
+constexpr int fwd_f64_chunkreg_lds() { return chunk_lds<NP, 8>(); }
+
+// Shared skeleton of the chunk-register bodies.  Per iteration the workgroup
+// stages TPW consecutive 16-column tiles of u (padded rows) and the geometric
+// factors of their elements in LDS, each compute wave runs its output chunk
+// for the TPW tiles and writes the results into an LDS output tile, and all
+// threads store the three planes as contiguous runs.  The next iteration's u
+// and G are loaded into registers while this iteration computes.
+template <typename T, int NP, int WPB, int KS, typename ChunkFn>
+__device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid, uint32_t nblk, char* lds,
+                                              ChunkFn&& chunk) {
+  constexpr int WORD = sizeof(T);
+  constexpr int TPW = chunk_tpw<NP, WORD>();
+  constexpr int LD = chunk_ld<NP>();
+  constexpr int SUP = TPW * 16 * NP;        // words of one plane of the super-tile
+  constexpr int NT = WAVE * WPB;
+  constexpr int NLD = (SUP + NT - 1) / NT;  // u words loaded per thread per iteration
+  constexpr int GMAX = TPW * 16 * 9;        // geometric-factor words of at most TPW*16 elements
+  constexpr int NG = (GMAX + NT - 1) / NT;  // G words loaded per thread per iteration
+  T* us = reinterpret_cast<T*>(lds);
+  T* ostg = reinterpret_cast<T*>(lds + align16(TPW * 16 * LD * WORD));
+  T* gs = reinterpret_cast<T*>(lds + align16(TPW * 16 * LD * WORD) + align16(3 * SUP * WORD));
+  const int tid = threadIdx.x;
+  const uint32_t nsup = (p.ntiles + TPW - 1) / TPW;
+  T ur[NLD];
+  T gr[NG];
+  auto load = [&](uint32_t st) {
+    const uint32_t c0 = st * TPW * 16;
+    const int cnt = (int)min((uint32_t)(TPW * 16), p.ncols - c0) * NP;
+    const T* __restrict__ src = p.u + (int64_t)c0 * NP;
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int x = tid + NT * q;
+      const T v = src[min(x, cnt - 1)];
+      ur[q] = x < cnt ? v : T(0);
+    }
+    const uint32_t k_lo = c0 / p.F;
+    const uint32_t k_hi = (c0 + (uint32_t)(cnt / NP) - 1) / p.F;
+    const int gcnt = (int)(k_hi - k_lo + 1) * 9;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) {
+      const int x = tid + NT * q;
+      const T gv = p.G[(int64_t)k_lo * 9 + min(x, gcnt - 1)];
+      gr[q] = x < gcnt ? gv : T(0);
+    }
+  };
+  uint32_t st = bid;
+  if (st < nsup) load(st);
+  for (; st < nsup; st += nblk) {
+    const uint32_t col0 = st * TPW * 16;
+    const int cnt = (int)min((uint32_t)(TPW * 16), p.ncols - col0) * NP;
+    const uint32_t k_lo = col0 / p.F;
+#pragma unroll
+    for (int q = 0; q < NLD; ++q) {
+      const int x = tid + NT * q;
+      if (x < SUP) us[(x / NP) * LD + (x % NP)] = ur[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NG; ++q)
+      if (tid + NT * q < GMAX) gs[tid + NT * q] = gr[q];
+    __syncthreads();
+    if (st + nblk < nsup) load(st + nblk);
+    chunk(us, ostg, gs, col0, k_lo);
+    __syncthreads();
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+      T* __restrict__ ob = p.out + bb * p.plane + (int64_t)col0 * NP;
+#pragma unroll
+      for (int q = 0; q < NLD; ++q) {
+        const int x = tid + NT * q;
+        if (x < cnt) ob[x] = ostg[bb * SUP + x];
+      }
+    }
+  }
+}
 
 template <int NP, int WPB>
 __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
@@ -153,15 +240,11 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
   static_assert(WPB >= Sh::NCHUNK, "one wave per output chunk");
   constexpr int KS = Sh::KS64;
   constexpr int LD = chunk_ld<NP>();
-  constexpr int TILE = 16 * NP;
-  constexpr int NT = WAVE * WPB;
-  constexpr int NLD = (TILE + NT - 1) / NT;  // u words loaded per thread per tile
-  double* us = reinterpret_cast<double*>(lds);
-  double* ostg = reinterpret_cast<double*>(lds + align16(16 * LD * 8));
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
+  constexpr int TPW = chunk_tpw<NP, 8>();
+  constexpr int SUP = TPW * 16 * NP;
+  const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
-  const int w = tid >> 6;
+  const int w = threadIdx.x >> 6;
   const bool mma = w < Sh::NCHUNK;
   const int ch = mma ? w : 0;
   // this wave's A operands, for the whole launch
@@ -172,48 +255,30 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
 #pragma unroll
     for (int s = 0; s < KS; ++s) areg[tt][s] = (mma && T < Sh::MT) ? afrag_f64<NP>(p.D, T, s, lane) : 0.0;
   }
-  double ur[NLD];
-  auto load_u = [&](uint32_t tt) {
-    const double* __restrict__ src = p.u + (int64_t)tt * TILE;
-    const int cnt = (int)min(16u, p.ncols - tt * 16) * NP;
+  auto chunk = [&](const double* us, double* ostg, const double* gs, uint32_t col0, uint32_t k_lo) {
+    if (!mma) return;
 #pragma unroll
-    for (int q = 0; q < NLD; ++q) {
-      const int x = tid + NT * q;
-      const double v = src[min(x, cnt - 1)];
-      ur[q] = x < cnt ? v : 0.0;
-    }
-  };
-  uint32_t t = bid;
-  if (t < p.ntiles) load_u(t);
-  for (; t < p.ntiles; t += nblk) {
-    const uint32_t col0 = t * 16;
-    const int cnt = (int)min(16u, p.ncols - col0) * NP;
-#pragma unroll
-    for (int q = 0; q < NLD; ++q) {
-      const int x = tid + NT * q;
-      if (x < TILE) us[(x / NP) * LD + (x % NP)] = ur[q];
-    }
-    __syncthreads();
-    if (t + nblk < p.ntiles) load_u(t + nblk);
-    if (mma) {
-      const uint32_t col = col0 + n;
-      const bool valid = col < p.ncols;
-      const uint32_t k = valid ? col / p.F : 0u;
-      double gk[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) gk[c] = p.G[(int64_t)k * 9 + c];
+    for (int tp = 0; tp < TPW; ++tp) {
+      const int cl = tp * 16 + n;  // column within the super-tile
       f64x4 acc[3];
 #pragma unroll
       for (int tt = 0; tt < 3; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
+      auto bval = [&](int s) {
+        const int j = 4 * s + g;
+        const double v = us[cl * LD + min(j, NP - 1)];
+        return j < NP ? v : 0.0;
+      };
+      double bcur = bval(0);
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        const int j = 4 * s + g;
-        const double bv = us[n * LD + min(j, NP - 1)];
-        const double b = j < NP ? bv : 0.0;
+        const double bnxt = s + 1 < KS ? bval(s + 1) : 0.0;
 #pragma unroll
         for (int tt = 0; tt < 3; ++tt)  // a missing third tile of the last chunk has zero operands
-          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[tt][s], b, acc[tt], 0, 0, 0);
+          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[tt][s], bcur, acc[tt], 0, 0, 0);
+        bcur = bnxt;
       }
+      const uint32_t col = col0 + cl;
+      const int e = (int)(min(col, p.ncols - 1) / p.F - k_lo);
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
         const int tau = 4 * ch + x;
@@ -222,19 +287,14 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
           const int l0 = 3 * x;
 #pragma unroll
           for (int bb = 0; bb < 3; ++bb)
-            ostg[bb * TILE + n * NP + i] = gk[bb] * acc[l0 >> 2][l0 & 3] +
-                                           gk[3 + bb] * acc[(l0 + 1) >> 2][(l0 + 1) & 3] +
-                                           gk[6 + bb] * acc[(l0 + 2) >> 2][(l0 + 2) & 3];
+            ostg[bb * SUP + cl * NP + i] = gs[e * 9 + bb] * acc[l0 >> 2][l0 & 3] +
+                                           gs[e * 9 + 3 + bb] * acc[(l0 + 1) >> 2][(l0 + 1) & 3] +
+                                           gs[e * 9 + 6 + bb] * acc[(l0 + 2) >> 2][(l0 + 2) & 3];
         }
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int bb = 0; bb < 3; ++bb) {
-      double* __restrict__ ob = p.out + bb * p.plane + (int64_t)col0 * NP;
-      for (int x = tid; x < cnt; x += NT) ob[x] = ostg[bb * TILE + x];
-    }
-  }
+  };
+  chunkreg_loop<double, NP, WPB, KS>(p, bid, nblk, lds, chunk);
 }
 
 // ------------------------------------------------------------------ split-BF16 staged
@@ -251,14 +311,24 @@ constexpr int fwd_f32s_staged_lds() {
   return (bf16_table_fits<NP>() ? 2 * bf16_table_entries<NP>() * 16 : 0) + WPB * 16 * NP * 4;
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+
+// u, out and every plane start 8-byte aligned: the staged split-BF16 body then
+// moves pairs of floats (512-byte runs per instruction, as the FP64 body does).
+__host__ __device__ inline bool f32_pairs_ok(const FwdArgs<float>& p) {
+  return (((uintptr_t)p.u | (uintptr_t)p.out) % 8 == 0) && (p.plane % 2 == 0);
+}
+
 template <int NP, int WPB>
 __device__ __forceinline__ void fwd_f32s_staged_body(const FwdArgs<float>& p, uint32_t bid, uint32_t nblk,
                                                      char* lds) {
   using Sh = Shape<NP>;
   constexpr bool ALDS = bf16_table_fits<NP>();
   constexpr int NTE = ALDS ? bf16_table_entries<NP>() : 0;
-  constexpr int TILE = 16 * NP;
+  constexpr int TILE = 16 * NP;  // even
   constexpr int NRAW = (TILE + WAVE - 1) / WAVE;
+  constexpr int NPAIR = (TILE / 2 + WAVE - 1) / WAVE;
+  constexpr int NREG = NRAW > 2 * NPAIR ? NRAW : 2 * NPAIR;
   Bf16x8Bits* ahi = reinterpret_cast<Bf16x8Bits*>(lds);
   Bf16x8Bits* alo = ahi + NTE;
   float* stg_all = reinterpret_cast<float*>(lds + 2 * NTE * 16);
@@ -272,30 +342,53 @@ __device__ __forceinline__ void fwd_f32s_staged_body(const FwdArgs<float>& p, ui
     }
     __syncthreads();
   }
+  const bool pairs = f32_pairs_ok(p);
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
   const uint32_t wave = threadIdx.x >> 6;
   float* stg = stg_all + wave * TILE;
   const uint32_t stride = nblk * WPB;
   uint32_t t = bid * WPB + wave;
-  float raw[NRAW];
-  auto load_raw = [&](uint32_t tt) {
+  float raw[NREG];
+  // a whole tile moves as pairs; a partial last tile word by word
+  auto load_raw = [&](uint32_t tt) __attribute__((always_inline)) {
     const float* __restrict__ src = p.u + (int64_t)tt * TILE;
     const int cnt = (int)min(16u, p.ncols - tt * 16) * NP;
+    if (pairs && cnt == TILE) {
 #pragma unroll
-    for (int q = 0; q < NRAW; ++q) {
-      const int x = lane + WAVE * q;
-      raw[q] = x < cnt ? src[x] : 0.0f;
+      for (int q = 0; q < NPAIR; ++q) {
+        const int x = lane + WAVE * q;
+        if (x < TILE / 2) {
+          const f32x2 v = reinterpret_cast<const f32x2*>(src)[x];
+          raw[2 * q] = v[0];
+          raw[2 * q + 1] = v[1];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NREG; ++q) {
+        const int x = lane + WAVE * q;
+        raw[q] = x < cnt ? src[x] : 0.0f;
+      }
     }
   };
   if (t < p.ntiles) load_raw(t);
   for (; t < p.ntiles; t += stride) {
     const uint32_t col0 = t * 16;
     const int cnt = (int)min(16u, p.ncols - col0) * NP;
+    const bool whole = pairs && cnt == TILE;
+    if (whole) {
 #pragma unroll
-    for (int q = 0; q < NRAW; ++q) {
-      const int x = lane + WAVE * q;
-      if (x < TILE) stg[x] = raw[q];
+      for (int q = 0; q < NPAIR; ++q) {
+        const int x = lane + WAVE * q;
+        if (x < TILE / 2) reinterpret_cast<f32x2*>(stg)[x] = f32x2{raw[2 * q], raw[2 * q + 1]};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NRAW; ++q) {
+        const int x = lane + WAVE * q;
+        if (x < TILE) stg[x] = raw[q];
+      }
     }
     wave_sync();
     Bf16x8Bits bh[Sh::KS16], bl[Sh::KS16];
@@ -346,10 +439,18 @@ __device__ __forceinline__ void fwd_f32s_staged_body(const FwdArgs<float>& p, ui
       }
       wave_sync();
       float* __restrict__ ob = p.out + bb * p.plane + (int64_t)col0 * NP;
+      if (whole) {
 #pragma unroll
-      for (int q = 0; q < NRAW; ++q) {
-        const int x = lane + WAVE * q;
-        if (x < cnt) ob[x] = stg[x];
+        for (int q = 0; q < NPAIR; ++q) {
+          const int x = lane + WAVE * q;
+          if (x < TILE / 2) reinterpret_cast<f32x2*>(ob)[x] = reinterpret_cast<const f32x2*>(stg)[x];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NRAW; ++q) {
+          const int x = lane + WAVE * q;
+          if (x < cnt) ob[x] = stg[x];
+        }
       }
       wave_sync();
     }
@@ -360,7 +461,7 @@ __device__ __forceinline__ void fwd_f32s_staged_body(const FwdArgs<float>& p, ui
 // ------------------------------------------------------------------ split-BF16 chunk-register
 
 template <int NP, int WPB>
-constexpr int fwd_f32s_chunkreg_lds() { return align16(16 * chunk_ld<NP>() * 4) + 3 * 16 * NP * 4; }
+constexpr int fwd_f32s_chunkreg_lds() { return chunk_lds<NP, 4>(); }
 
 template <int NP, int WPB>
 __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, uint32_t bid, uint32_t nblk,
@@ -369,15 +470,11 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
   static_assert(WPB >= Sh::NCHUNK, "one wave per output chunk");
   constexpr int KS = Sh::KS16;
   constexpr int LD = chunk_ld<NP>();
-  constexpr int TILE = 16 * NP;
-  constexpr int NT = WAVE * WPB;
-  constexpr int NLD = (TILE + NT - 1) / NT;
-  float* us = reinterpret_cast<float*>(lds);
-  float* ostg = reinterpret_cast<float*>(lds + align16(16 * LD * 4));
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
+  constexpr int TPW = chunk_tpw<NP, 4>();
+  constexpr int SUP = TPW * 16 * NP;
+  const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
-  const int w = tid >> 6;
+  const int w = threadIdx.x >> 6;
   const bool mma = w < Sh::NCHUNK;
   const int ch = mma ? w : 0;
   Bf16x8Bits ah[3][KS], al[3][KS];
@@ -394,36 +491,11 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
       }
     }
   }
-  float ur[NLD];
-  auto load_u = [&](uint32_t tt) {
-    const float* __restrict__ src = p.u + (int64_t)tt * TILE;
-    const int cnt = (int)min(16u, p.ncols - tt * 16) * NP;
+  auto chunk = [&](const float* us, float* ostg, const float* gs, uint32_t col0, uint32_t k_lo) {
+    if (!mma) return;
 #pragma unroll
-    for (int q = 0; q < NLD; ++q) {
-      const int x = tid + NT * q;
-      const float v = src[min(x, cnt - 1)];
-      ur[q] = x < cnt ? v : 0.0f;
-    }
-  };
-  uint32_t t = bid;
-  if (t < p.ntiles) load_u(t);
-  for (; t < p.ntiles; t += nblk) {
-    const uint32_t col0 = t * 16;
-    const int cnt = (int)min(16u, p.ncols - col0) * NP;
-#pragma unroll
-    for (int q = 0; q < NLD; ++q) {
-      const int x = tid + NT * q;
-      if (x < TILE) us[(x / NP) * LD + (x % NP)] = ur[q];
-    }
-    __syncthreads();
-    if (t + nblk < p.ntiles) load_u(t + nblk);
-    if (mma) {
-      const uint32_t col = col0 + n;
-      const bool valid = col < p.ncols;
-      const uint32_t k = valid ? col / p.F : 0u;
-      float gk[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) gk[c] = p.G[(int64_t)k * 9 + c];
+    for (int tp = 0; tp < TPW; ++tp) {
+      const int cl = tp * 16 + n;
       f32x4 acc[3];
 #pragma unroll
       for (int tt = 0; tt < 3; ++tt) acc[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
@@ -433,7 +505,7 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int j = 32 * s + 8 * g + e;
-          const float v = us[n * LD + min(j, NP - 1)];
+          const float v = us[cl * LD + min(j, NP - 1)];
           split_bf16(j < NP ? v : 0.0f, bh.v[e], bl.v[e]);
         }
 #pragma unroll
@@ -443,6 +515,8 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
           acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah[tt][s]), as_bf16x8(bh), acc[tt], 0, 0, 0);
         }
       }
+      const uint32_t col = col0 + cl;
+      const int e = (int)(min(col, p.ncols - 1) / p.F - k_lo);
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
         const int tau = 4 * ch + x;
@@ -451,19 +525,14 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
           const int l0 = 3 * x;
 #pragma unroll
           for (int bb = 0; bb < 3; ++bb)
-            ostg[bb * TILE + n * NP + i] = gk[bb] * acc[l0 >> 2][l0 & 3] +
-                                           gk[3 + bb] * acc[(l0 + 1) >> 2][(l0 + 1) & 3] +
-                                           gk[6 + bb] * acc[(l0 + 2) >> 2][(l0 + 2) & 3];
+            ostg[bb * SUP + cl * NP + i] = gs[e * 9 + bb] * acc[l0 >> 2][l0 & 3] +
+                                           gs[e * 9 + 3 + bb] * acc[(l0 + 1) >> 2][(l0 + 1) & 3] +
+                                           gs[e * 9 + 6 + bb] * acc[(l0 + 2) >> 2][(l0 + 2) & 3];
         }
       }
     }
-    __syncthreads();
-#pragma unroll
-    for (int bb = 0; bb < 3; ++bb) {
-      float* __restrict__ ob = p.out + bb * p.plane + (int64_t)col0 * NP;
-      for (int x = tid; x < cnt; x += NT) ob[x] = ostg[bb * TILE + x];
-    }
-  }
+  };
+  chunkreg_loop<float, NP, WPB, KS>(p, bid, nblk, lds, chunk);
 }
 
 }  // namespace dgvol

@@ -280,16 +280,20 @@ static int lds_bytes(int form, int Np, int body) {
   return 0;
 }
 
-// Tiles one workgroup processes per step of its loop.
-static inline uint32_t tiles_per_block(int body) { return body == BODY_STAGED ? FWD_WPB : 1; }
+// 16-column tiles one workgroup processes per step of its loop.
+static inline uint32_t tiles_per_block(int form, int Np, int body) {
+  if (body == BODY_STAGED) return FWD_WPB;
+  if (form != DG_FORM_F64) return chunk_tpw<4, 4>();
+  return Np >= 120 ? chunk_tpw<120, 8>() : chunk_tpw<4, 8>();
+}
 
 template <typename Kern, typename Args>
-static dg_status launch_persistent(Kern kern, const Args& args, uint32_t ntiles, int body, int lds,
-                                   hipStream_t stream) {
+static dg_status launch_persistent(Kern kern, const Args& args, uint32_t ntiles, int form, int Np, int body,
+                                   int lds, hipStream_t stream) {
   int err = DG_OK;
   const int cap = resident_blocks(kern, WAVE * FWD_WPB, lds, &err);
   if (err != DG_OK) return err;
-  const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, tiles_per_block(body)), (uint32_t)cap);
+  const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, tiles_per_block(form, Np, body)), (uint32_t)cap);
   hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * FWD_WPB), (size_t)lds, stream, args);
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
@@ -298,19 +302,19 @@ template <int NP>
 static dg_status launch_fwd_f64(const FwdArgs<double>& p, hipStream_t stream) {
   if constexpr (f64_staged_ok<NP>()) {
     if (default_body_f64(NP) == BODY_STAGED)
-      return launch_persistent(fwd_f64_kernel<NP, BODY_STAGED>, p, p.ntiles, BODY_STAGED,
+      return launch_persistent(fwd_f64_kernel<NP, BODY_STAGED>, p, p.ntiles, DG_FORM_F64, NP, BODY_STAGED,
                                f64_lds<NP, BODY_STAGED>(), stream);
   }
-  return launch_persistent(fwd_f64_kernel<NP, BODY_CHUNKREG>, p, p.ntiles, BODY_CHUNKREG,
+  return launch_persistent(fwd_f64_kernel<NP, BODY_CHUNKREG>, p, p.ntiles, DG_FORM_F64, NP, BODY_CHUNKREG,
                            f64_lds<NP, BODY_CHUNKREG>(), stream);
 }
 
 template <int NP>
 static dg_status launch_fwd_f32s(const FwdArgs<float>& p, hipStream_t stream) {
   if (default_body_f32s(NP) == BODY_STAGED)
-    return launch_persistent(fwd_f32s_kernel<NP, BODY_STAGED>, p, p.ntiles, BODY_STAGED,
+    return launch_persistent(fwd_f32s_kernel<NP, BODY_STAGED>, p, p.ntiles, DG_FORM_F32S, NP, BODY_STAGED,
                              f32s_lds<NP, BODY_STAGED>(), stream);
-  return launch_persistent(fwd_f32s_kernel<NP, BODY_CHUNKREG>, p, p.ntiles, BODY_CHUNKREG,
+  return launch_persistent(fwd_f32s_kernel<NP, BODY_CHUNKREG>, p, p.ntiles, DG_FORM_F32S, NP, BODY_CHUNKREG,
                            f32s_lds<NP, BODY_CHUNKREG>(), stream);
 }
 
@@ -494,7 +498,7 @@ dg_status dg_volume_batched(const dg_group* groups, int32_t ngroups, int32_t F, 
     gd.out = gr.out;
     const double per_tile = gr.cost > 0.0 ? gr.cost : tile_cost_estimate(form, gr.Np, (uint32_t)F);
     cost[ng] = per_tile * gd.ntiles;
-    max_blocks[ng] = ceil_div(gd.ntiles, tiles_per_block(body));
+    max_blocks[ng] = ceil_div(gd.ntiles, tiles_per_block(form, gr.Np, body));
     total_cost += cost[ng];
     lds = std::max(lds, lds_bytes(form, gr.Np, body));
     ++ng;
