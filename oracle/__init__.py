@@ -27,12 +27,12 @@ condition-scaled criteria documented next to each test.
 from .refelem import (num_nodes, order_from_np, equispaced_nodes, monomial_exponents,
                       vandermonde, derivative_matrices)
 from .geometry import jacobians, geometric_factors, physical_nodes
-from .kernels import (volume, volume_adjoint, volume_split_bf16, bf16_round_f32,
+from .kernels import (volume, volume_adjoint, volume_grad_d, volume_split_bf16, bf16_round_f32,
                       library_path, build_library, num_threads)
 
 __all__ = [
     "num_nodes", "order_from_np", "equispaced_nodes", "monomial_exponents", "vandermonde",
     "derivative_matrices", "jacobians", "geometric_factors", "physical_nodes",
-    "volume", "volume_adjoint", "volume_split_bf16", "bf16_round_f32",
+    "volume", "volume_adjoint", "volume_grad_d", "volume_split_bf16", "bf16_round_f32",
     "library_path", "build_library", "num_threads",
 ]

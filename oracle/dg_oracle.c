@@ -12,6 +12,7 @@
  *   gout [3][K][F][Np]   cotangent of out
  *   gu   [K][F][Np]      cotangent of u
  *   gG   [K][9]          cotangent of G
+ *   gD   [3][Np][Np]     cotangent of D
  *
  * The volume term of nodal DG on affine elements (the PDE-solver use case in
  * the paper's Introduction) is, for every element k and field f,
@@ -21,6 +22,7 @@
  *   W_a[i]       = sum_b G[k][3a+b] gout_b[i]
  *   gu[k][f][j]  = sum_a sum_i D[a][i][j] W_a[i]
  *   gG[k][3a+b]  = sum_f sum_i gout_b[k][f][i] R_a[k][f][i]
+ *   gD[a][i][j]  = sum_k sum_f W_a[k][f][i] u[k][f][j]
  * All sums run in ascending index order; compiled with -ffp-contract=off so
  * every product is rounded before it is added.  Elements are independent and
  * are shared across OpenMP threads; each output is written by one thread.
@@ -95,6 +97,33 @@ void oracle_volume_adjoint(const double *D, const double *G, const double *u, co
                 }
         }
         for (int c = 0; c < 9; ++c) gG[9 * k + c] = acc[c];
+    }
+}
+
+/* Cotangent of D: gD[a][i][j] = sum over (k, f) ascending of W_a[i] u[k][f][j],
+ * with W_a[i] = sum_b G[k][3a+b] gout_b[k][f][i] as in the adjoint above.  The
+ * reduction runs over every element, so each OpenMP thread owns whole rows
+ * (a, i) of gD and recomputes their W values; the result does not depend on
+ * the thread count. */
+void oracle_volume_grad_d(const double *G, const double *u, const double *gout, double *gD,
+                          int64_t K, int32_t Np, int32_t F) {
+    const int64_t plane = K * (int64_t)F * Np;
+#pragma omp parallel for schedule(static)
+    for (int32_t r = 0; r < 3 * Np; ++r) {
+        const int a = r / Np;
+        const int32_t i = r % Np;
+        double *row = gD + (int64_t)r * Np;
+        for (int32_t j = 0; j < Np; ++j) row[j] = 0.0;
+        for (int64_t k = 0; k < K; ++k) {
+            const double *g = G + 9 * k;
+            for (int32_t f = 0; f < F; ++f) {
+                const int64_t col = (k * F + f) * (int64_t)Np;
+                const double w = g[3 * a + 0] * gout[0 * plane + col + i]
+                               + g[3 * a + 1] * gout[1 * plane + col + i]
+                               + g[3 * a + 2] * gout[2 * plane + col + i];
+                for (int32_t j = 0; j < Np; ++j) row[j] += w * u[col + j];
+            }
+        }
     }
 }
 

@@ -45,6 +45,8 @@ def _load():
     lib.oracle_volume.restype = None
     lib.oracle_volume_adjoint.argtypes = [P, P, P, P, P, P, I64, I32, I32]
     lib.oracle_volume_adjoint.restype = None
+    lib.oracle_volume_grad_d.argtypes = [P, P, P, P, I64, I32, I32]
+    lib.oracle_volume_grad_d.restype = None
     lib.oracle_volume_split_bf16.argtypes = [P, P, P, P, I64, I32, I32]
     lib.oracle_volume_split_bf16.restype = None
     lib.oracle_bf16_round.argtypes = [P, P, I64]
@@ -97,6 +99,20 @@ def volume_adjoint(D, G, u, gout):
     _load().oracle_volume_adjoint(D.ctypes.data, G.ctypes.data, u.ctypes.data, gout.ctypes.data,
                                   gu.ctypes.data, gG.ctypes.data, K, Np, F)
     return gu, gG
+
+
+def volume_grad_d(G, u, gout):
+    """Cotangent of D for cotangent gout (3,K,F,Np): gD (3,Np,Np), a sum over all elements."""
+    G, u, gout = _c(G, np.float64), _c(u, np.float64), _c(gout, np.float64)
+    K, F, Np = u.shape
+    if G.shape != (K, 9):
+        raise ValueError(f"G must be ({K}, 9), got {G.shape}")
+    if gout.shape != (3, K, F, Np):
+        raise ValueError(f"gout must be (3, {K}, {F}, {Np}), got {gout.shape}")
+    gD = np.empty((3, Np, Np))
+    _load().oracle_volume_grad_d(G.ctypes.data, u.ctypes.data, gout.ctypes.data, gD.ctypes.data,
+                                 K, Np, F)
+    return gD
 
 
 def volume_split_bf16(D32, G32, u32):

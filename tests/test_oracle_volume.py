@@ -3,7 +3,8 @@
 None of these re-types the oracle's formulas: each compares against exact
 calculus (polynomials differentiated analytically), a one-element brute force
 through the physical Vandermonde matrix (no D, no G), exact adjoint
-identities, central finite differences, or an independent BF16 rounding.
+identities (in u, G and D), central finite differences, additivity of the
+cross-element D cotangent, or an independent BF16 rounding.
 """
 
 import numpy as np
@@ -277,6 +278,67 @@ def test_adjoint_finite_differences():
     fd_G = np.array(fd_G)
     an_G = np.array([gG[ix] for ix in idx_G])
     assert np.abs(fd_G - an_G).max() <= 1e-6 * np.abs(an_G).max()
+
+
+@pytest.mark.parametrize("N,F", [(1, 1), (2, 3), (4, 2), (7, 1)])
+def test_grad_d_identity(N, F):
+    """<fwd(u,G,D), w> = <D, gD> for any D: out is linear in D as well.
+
+    A random D (no zero row sums, no symmetry) so that a transposed gD or a
+    gD built from a shifted u cannot pass by accident."""
+    rng = np.random.default_rng(90 + N)
+    K = 41
+    Np = oracle.num_nodes(N)
+    D = rng.standard_normal((3, Np, Np))
+    G = oracle.geometric_factors(synth.tet_vertices(K, seed=91))
+    u = rng.standard_normal((K, F, Np))
+    w = rng.standard_normal((3, K, F, Np))
+    gD = oracle.volume_grad_d(G, u, w)
+    s0 = np.sum(oracle.volume(D, G, u) * w)
+    scale = np.sum(np.abs(D)) * np.abs(gD).max() + abs(s0)
+    assert abs(np.sum(D * gD) - s0) <= 1e-13 * scale
+    # each of the three matrices separately: only D_a enters direction a
+    for a in range(3):
+        Da = np.zeros_like(D)
+        Da[a] = D[a]
+        sa = np.sum(oracle.volume(Da, G, u) * w)
+        assert abs(np.sum(D[a] * gD[a]) - sa) <= 1e-13 * scale
+
+
+def test_grad_d_additive_over_elements():
+    """gD is a sum over elements: splitting the mesh splits it."""
+    rng = np.random.default_rng(95)
+    N, K, F = 3, 50, 2
+    Np = oracle.num_nodes(N)
+    G = oracle.geometric_factors(synth.tet_vertices(K, seed=96))
+    u = rng.standard_normal((K, F, Np))
+    w = rng.standard_normal((3, K, F, Np))
+    whole = oracle.volume_grad_d(G, u, w)
+    parts = oracle.volume_grad_d(G[:17], u[:17], w[:, :17]) + oracle.volume_grad_d(G[17:], u[17:], w[:, 17:])
+    assert np.abs(whole - parts).max() <= 1e-13 * np.abs(whole).max()
+    assert np.all(oracle.volume_grad_d(G[:0], u[:0], w[:, :0]) == 0.0)
+
+
+def test_grad_d_finite_differences():
+    """Loss = sum(out^2); central differences in entries of D, h = 1e-6."""
+    rng = np.random.default_rng(97)
+    N, K, F = 4, 64, 3
+    Np = oracle.num_nodes(N)
+    D = oracle.derivative_matrices(N)
+    G = oracle.geometric_factors(synth.tet_vertices(K, seed=98))
+    u = rng.uniform(-1, 1, (K, F, Np))
+    gD = oracle.volume_grad_d(G, u, 2 * oracle.volume(D, G, u))
+    h = 1e-6
+    idx = [(a, int(rng.integers(0, Np)), int(rng.integers(0, Np))) for a in range(3) for _ in range(8)]
+    fd = []
+    for ix in idx:
+        Dp, Dm = D.copy(), D.copy()
+        Dp[ix] += h
+        Dm[ix] -= h
+        fd.append((np.sum(oracle.volume(Dp, G, u) ** 2) - np.sum(oracle.volume(Dm, G, u) ** 2)) / (2 * h))
+    fd = np.array(fd)
+    an = np.array([gD[ix] for ix in idx])
+    assert np.abs(fd - an).max() <= 1e-6 * np.abs(an).max()
 
 
 # ---------------------------------------------------------------- split-BF16
