@@ -103,6 +103,34 @@ dg_status dg_volume_adjoint(const double *D, const double *G, const double *u,
                             int64_t K, int32_t Np, int32_t F, void *stream);
 
 /*
+ * Cotangent of the reference differentiation matrices D, FP64.  The forward
+ * map is linear in D; for the cotangent gout of out it is the sum over all
+ * element columns (k, f)
+ *   gD[a][i][j] = sum_k sum_f W_a[i] * u[k][f][j],
+ *   W_a[i]      = sum_b G[k][3a+b] gout[b][k][f][i]   (as in dg_volume_adjoint),
+ * i.e. the reverse-mode rule for a matrix product applied to the reference
+ * derivative D_a u of every element and field.
+ *   G [K][9], u [K][F][Np], gout [3][K][F][Np] (read); gD [3][Np][Np] (written,
+ *   never accumulated; zeros when K == 0).
+ *   work: device scratch of at least dg_volume_grad_d_workspace(K, Np, F)
+ *   bytes, owned by the caller, 8-byte aligned; its contents on entry are
+ *   ignored and on return are unspecified.  Calls that share one work buffer
+ *   must be ordered on one stream.
+ * The columns are split into a number of partial sums fixed by (K, F) alone
+ * and added in a fixed order, so the result is the same bit for bit on every
+ * run and every device.  No D argument: gD does not depend on D.
+ * Errors: DG_EINVAL (null or misaligned pointer, work_bytes too small,
+ *         K < 0, F < 1), DG_EUNSUPPORTED (Np), DG_ELAUNCH.
+ */
+dg_status dg_volume_grad_d(const double *G, const double *u, const double *gout, double *gD,
+                           void *work, uint64_t work_bytes,
+                           int64_t K, int32_t Np, int32_t F, void *stream);
+
+/* Scratch bytes dg_volume_grad_d needs for (K, Np, F), written to *bytes (may
+ * be 0).  Pure host computation.  Errors: DG_EINVAL, DG_EUNSUPPORTED. */
+dg_status dg_volume_grad_d_workspace(int64_t K, int32_t Np, int32_t F, uint64_t *bytes);
+
+/*
  * Forward volume derivative with FP32 storage and split-BF16 products.
  * Same layouts as dg_volume with float elements.  Each FP32 operand x of the
  * product D_a u is split into x_hi = bf16(x) and x_lo = bf16(x - x_hi)

@@ -40,12 +40,27 @@ struct FwdArgs {
 
 // ------------------------------------------------------------------ FP64 staged
 
-template <int NP, int WPB>
-constexpr int fwd_f64_staged_lds() { return align16(fwd_table_doubles<NP>() * 8) + WPB * 16 * NP * 8; }
+// 16-column tiles a wave of the FP64 staged body takes per iteration.  A tile
+// of a low order is only 16 Np doubles, too few bytes in flight per wave to
+// cover the memory latency; several tiles per iteration (with their geometric
+// factors fetched as one contiguous run) raise that.
+template <int NP>
+constexpr int staged_tpi() { return NP <= 4 ? 4 : (NP <= 20 ? 2 : 1); }
+
+// Per wave: the u / output staging buffer, plus, with several tiles per
+// iteration, room for the geometric factors of up to 16 TPI elements.
+template <int NP>
+constexpr int staged_wave_doubles() {
+  constexpr int TPI = staged_tpi<NP>();
+  return TPI * 16 * NP + (TPI > 1 ? TPI * 16 * 9 : 0);
+}
 
 template <int NP, int WPB>
-__device__ __forceinline__ void fwd_f64_staged_body(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
-                                                    char* lds) {
+constexpr int fwd_f64_staged_lds() { return align16(fwd_table_doubles<NP>() * 8) + WPB * staged_wave_doubles<NP>() * 8; }
+
+template <int NP, int WPB>
+__device__ __forceinline__ void fwd_f64_staged_single(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
+                                                      char* lds) {
   using Sh = Shape<NP>;
   constexpr int NFRAG = fwd_table_doubles<NP>();
   constexpr int TILE = 16 * NP;
@@ -137,6 +152,150 @@ __device__ __forceinline__ void fwd_f64_staged_body(const FwdArgs<double>& p, ui
     }
     if (t + stride < p.ntiles) load_raw(t + stride);
   }
+}
+
+// Several tiles per iteration (low orders).  A wave takes TPI consecutive
+// tiles -- 16 TPI columns, one contiguous run of u and of each output plane --
+// and fetches the geometric factors of their elements, which are contiguous in
+// G, as one run too.  Both are loaded into registers one iteration ahead and
+// staged through the wave's LDS buffer.
+template <int NP, int WPB>
+__device__ __forceinline__ void fwd_f64_staged_multi(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
+                                                     char* lds) {
+  using Sh = Shape<NP>;
+  constexpr int TPI = staged_tpi<NP>();
+  constexpr int NFRAG = fwd_table_doubles<NP>();
+  constexpr int TILE = 16 * NP;
+  constexpr int RUN = TPI * TILE;                  // doubles of u per iteration
+  constexpr int NRAW = (RUN + WAVE - 1) / WAVE;
+  constexpr int GW = TPI * 16 * 9;                 // G words of at most 16 TPI elements
+  constexpr int NGR = (GW + WAVE - 1) / WAVE;
+  double* afr = reinterpret_cast<double*>(lds);
+  for (int e = threadIdx.x; e < NFRAG; e += WAVE * WPB) {
+    const int ts = e >> 6;
+    afr[e] = afrag_f64<NP>(p.D, ts / Sh::KS64, ts % Sh::KS64, e & 63);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const uint32_t wave = threadIdx.x >> 6;
+  double* su = reinterpret_cast<double*>(lds + align16(NFRAG * 8)) + wave * staged_wave_doubles<NP>();
+  double* sg = su + RUN;
+  const uint32_t nrun = (p.ntiles + TPI - 1) / TPI;
+  const uint32_t stride = nblk * WPB;
+  uint32_t t = bid * WPB + wave;
+  double raw[NRAW], graw[NGR];
+  // first element of the run and the number of its G words
+  auto run_elems = [&](uint32_t tt, uint32_t& e0, int& ng) __attribute__((always_inline)) {
+    const uint32_t c0 = tt * (16 * TPI);
+    const uint32_t c1 = min(c0 + 16 * TPI, p.ncols) - 1;
+    e0 = c0 / p.F;
+    ng = (int)(c1 / p.F - e0 + 1) * 9;
+  };
+  auto load_run = [&](uint32_t tt) __attribute__((always_inline)) {
+    const uint32_t c0 = tt * (16 * TPI);
+    const double* __restrict__ src = p.u + (int64_t)c0 * NP;
+    const int cnt = (int)min(16u * TPI, p.ncols - c0) * NP;
+#pragma unroll
+    for (int q = 0; q < NRAW; ++q) {
+      const int x = lane + WAVE * q;
+      raw[q] = x < cnt ? src[x] : 0.0;
+    }
+    uint32_t e0;
+    int ng;
+    run_elems(tt, e0, ng);
+    const double* __restrict__ gsrc = p.G + (int64_t)e0 * 9;
+#pragma unroll
+    for (int q = 0; q < NGR; ++q) {
+      const int x = lane + WAVE * q;
+      graw[q] = x < ng ? gsrc[x] : 0.0;
+    }
+  };
+  if (t < nrun) load_run(t);
+  for (; t < nrun; t += stride) {
+    const uint32_t col0 = t * (16 * TPI);
+    const int cnt = (int)min(16u * TPI, p.ncols - col0) * NP;
+    uint32_t e0;
+    int ng;
+    run_elems(t, e0, ng);
+#pragma unroll
+    for (int q = 0; q < NRAW; ++q) {
+      const int x = lane + WAVE * q;
+      if (x < RUN) su[x] = raw[q];
+    }
+#pragma unroll
+    for (int q = 0; q < NGR; ++q) {
+      const int x = lane + WAVE * q;
+      if (x < GW) sg[x] = graw[q];
+    }
+    wave_sync();
+    double b[TPI][Sh::KS64];
+#pragma unroll
+    for (int r = 0; r < TPI; ++r) {
+#pragma unroll
+      for (int s = 0; s < Sh::KS64; ++s) {
+        const int j = 4 * s + g;
+        b[r][s] = j < NP ? su[r * TILE + n * NP + j] : 0.0;
+      }
+    }
+    wave_sync();
+    if (t + stride < nrun) load_run(t + stride);
+    f64x4 acc[TPI][Sh::MT];
+#pragma unroll
+    for (int r = 0; r < TPI; ++r) {
+#pragma unroll
+      for (int T = 0; T < Sh::MT; ++T) acc[r][T] = f64x4{0.0, 0.0, 0.0, 0.0};
+    }
+    // one k-step's A operands at a time, shared by the TPI tiles
+#pragma unroll
+    for (int s = 0; s < Sh::KS64; ++s) {
+      double a[Sh::MT];
+#pragma unroll
+      for (int T = 0; T < Sh::MT; ++T) a[T] = afr[(T * Sh::KS64 + s) * WAVE + lane];
+#pragma unroll
+      for (int r = 0; r < TPI; ++r) {
+#pragma unroll
+        for (int T = 0; T < Sh::MT; ++T)
+          acc[r][T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[T], b[r][s], acc[r][T], 0, 0, 0);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+#pragma unroll
+      for (int r = 0; r < TPI; ++r) {
+        const uint32_t col = col0 + 16 * r + n;
+        const int ge = col < p.ncols ? (int)(col / p.F - e0) * 9 : 0;
+        const double g0 = sg[ge + bb], g1 = sg[ge + 3 + bb], g2 = sg[ge + 6 + bb];
+#pragma unroll
+        for (int tau = 0; tau < Sh::TRIP; ++tau) {
+          const int i = 4 * tau + g;
+          const int s0 = 3 * tau;
+          const double v = g0 * acc[r][s0 >> 2][s0 & 3] + g1 * acc[r][(s0 + 1) >> 2][(s0 + 1) & 3] +
+                           g2 * acc[r][(s0 + 2) >> 2][(s0 + 2) & 3];
+          if (i < NP) su[r * TILE + n * NP + i] = v;
+        }
+      }
+      wave_sync();
+      double* __restrict__ ob = p.out + bb * p.plane + (int64_t)col0 * NP;
+#pragma unroll
+      for (int q = 0; q < NRAW; ++q) {
+        const int x = lane + WAVE * q;
+        if (x < cnt) ob[x] = su[x];
+      }
+      wave_sync();
+    }
+    (void)ng;
+  }
+}
+
+template <int NP, int WPB>
+__device__ __forceinline__ void fwd_f64_staged_body(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
+                                                    char* lds) {
+  if constexpr (staged_tpi<NP>() > 1)
+    fwd_f64_staged_multi<NP, WPB>(p, bid, nblk, lds);
+  else
+    fwd_f64_staged_single<NP, WPB>(p, bid, nblk, lds);
 }
 
 // ------------------------------------------------------------------ FP64 chunk-register

@@ -17,6 +17,7 @@
 #include "dgvol_adjoint.hpp"
 #include "dgvol_device.hpp"
 #include "dgvol_forward.hpp"
+#include "dgvol_gradd.hpp"
 #include "dgvol_layout.hpp"
 
 namespace dgvol {
@@ -282,7 +283,8 @@ static int lds_bytes(int form, int Np, int body) {
 
 // 16-column tiles one workgroup processes per step of its loop.
 static inline uint32_t tiles_per_block(int form, int Np, int body) {
-  if (body == BODY_STAGED) return FWD_WPB;
+  if (body == BODY_STAGED)
+    return form == DG_FORM_F64 ? FWD_WPB * (Np <= 4 ? staged_tpi<4>() : Np <= 20 ? staged_tpi<20>() : 1) : FWD_WPB;
   if (form != DG_FORM_F64) return chunk_tpw<4, 4>();
   return Np >= 120 ? chunk_tpw<120, 8>() : chunk_tpw<4, 8>();
 }
@@ -340,6 +342,30 @@ static dg_status launch_adj_f64(const double* D, const double* G, const double* 
     hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * ADJ_WPB), 0, stream, D, G, u, gout, gu, gG, (uint32_t)K,
                        (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
   }
+  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+}
+
+// Partial sums of the D cotangent: a pure function of the problem size, so
+// the result does not depend on the device.
+static uint32_t gd_parts(int64_t K, int32_t F) {
+  const uint32_t nchunks = ceil_div((uint64_t)K * (uint64_t)F, GD_CHUNK_MAX);
+  return std::min<uint32_t>(nchunks, GD_MAXPART);
+}
+
+template <int NP>
+static dg_status launch_gd_f64(const double* G, const double* u, const double* gout, double* gD, double* work,
+                               int64_t K, int32_t F, hipStream_t stream) {
+  const uint64_t ncols = (uint64_t)K * (uint64_t)F;
+  const uint32_t npart = gd_parts(K, F);
+  if (npart > 0) {
+    const GdArgs p{G, u, gout, work, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP,
+                   ceil_div(ncols, GD_CHUNK_MAX), npart};
+    hipLaunchKernelGGL(gd_partial_kernel<NP>, dim3(npart * GdShape<NP>::NSPLIT), dim3(GdShape<NP>::NTH), 0, stream,
+                       p);
+  }
+  const uint32_t n = 3u * NP * NP;
+  hipLaunchKernelGGL(gd_reduce_kernel, dim3(ceil_div(n, 64)), dim3(64 * GD_RED_PG), 0, stream, work, gD, npart,
+                     n);
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
 
@@ -456,6 +482,31 @@ dg_status dg_volume_adjoint(const double* D, const double* G, const double* u, c
       !aligned(gG, 8))
     return DG_EINVAL;
   DGVOL_DISPATCH(launch_adj_f64, D, G, u, gout, gu, gG, K, F, (hipStream_t)stream)
+}
+
+dg_status dg_volume_grad_d_workspace(int64_t K, int32_t Np, int32_t F, uint64_t* bytes) {
+  if (!bytes) return DG_EINVAL;
+  bool noop = false;
+  const dg_status st = check_common(K, Np, F, &noop);
+  if (st != DG_OK) return st;
+  *bytes = (uint64_t)gd_parts(K, F) * 3u * (uint64_t)Np * (uint64_t)Np * sizeof(double);
+  return DG_OK;
+}
+
+dg_status dg_volume_grad_d(const double* G, const double* u, const double* gout, double* gD, void* work,
+                           uint64_t work_bytes, int64_t K, int32_t Np, int32_t F, void* stream) {
+  bool noop = false;
+  const dg_status st = check_common(K, Np, F, &noop);
+  if (st != DG_OK) return st;
+  if (!gD || !aligned(gD, 8)) return DG_EINVAL;
+  uint64_t need = 0;
+  dg_volume_grad_d_workspace(K, Np, F, &need);
+  if (!noop) {
+    if (!G || !u || !gout || !work) return DG_EINVAL;
+    if (!aligned(G, 8) || !aligned(u, 8) || !aligned(gout, 8) || !aligned(work, 8)) return DG_EINVAL;
+    if (work_bytes < need) return DG_EINVAL;
+  }
+  DGVOL_DISPATCH(launch_gd_f64, G, u, gout, gD, static_cast<double*>(work), K, F, (hipStream_t)stream)
 }
 
 #undef DGVOL_DISPATCH

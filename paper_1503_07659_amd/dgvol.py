@@ -72,6 +72,10 @@ def load_library(path=None):
     lib.dg_volume.restype = I32
     lib.dg_volume_adjoint.argtypes = [P, P, P, P, P, P, I64, I32, I32, P]
     lib.dg_volume_adjoint.restype = I32
+    lib.dg_volume_grad_d.argtypes = [P, P, P, P, P, ctypes.c_uint64, I64, I32, I32, P]
+    lib.dg_volume_grad_d.restype = I32
+    lib.dg_volume_grad_d_workspace.argtypes = [I64, I32, I32, ctypes.POINTER(ctypes.c_uint64)]
+    lib.dg_volume_grad_d_workspace.restype = I32
     lib.dg_volume_f32s.argtypes = [P, P, P, P, I64, I32, I32, P]
     lib.dg_volume_f32s.restype = I32
     lib.dg_stream_calibrate.argtypes = [P, P, I64, I32, P]
@@ -162,6 +166,40 @@ def dg_volume_adjoint(D, G, u, gout, gu=None, gG=None):
     return gu, gG
 
 
+def grad_d_workspace_bytes(K, Np, F):
+    """Scratch bytes dg_volume_grad_d needs for (K, Np, F) (host computation)."""
+    n = ctypes.c_uint64(0)
+    _raise_on(load_library().dg_volume_grad_d_workspace(int(K), int(Np), int(F), ctypes.byref(n)),
+              "dg_volume_grad_d_workspace")
+    return int(n.value)
+
+
+def dg_volume_grad_d(G, u, gout, gD=None, work=None):
+    """FP64 cotangent of D (3, Np, Np) for the cotangent gout (3, K, F, Np) of dg_volume.
+
+    ``work`` is optional device scratch (uint8, at least ``grad_d_workspace_bytes``);
+    one is allocated when it is not given."""
+    _check_tensor("u", u, torch.float64, tuple(u.shape))
+    K, F, Np = _sizes(u, None)
+    dev = u.device
+    _check_tensor("G", G, torch.float64, (K, 9), dev)
+    _check_tensor("gout", gout, torch.float64, (3, K, F, Np), dev)
+    if gD is None:
+        gD = torch.empty((3, Np, Np), dtype=torch.float64, device=dev)
+    _check_tensor("gD", gD, torch.float64, (3, Np, Np), dev)
+    need = grad_d_workspace_bytes(K, Np, F)
+    if work is None:
+        work = torch.empty(max(need, 8), dtype=torch.uint8, device=dev)
+    if not isinstance(work, torch.Tensor) or work.device != dev or not work.is_contiguous():
+        raise ValueError("work must be a contiguous tensor on the device of u")
+    nbytes = work.numel() * work.element_size()
+    with torch.cuda.device(dev):
+        st = load_library().dg_volume_grad_d(G.data_ptr(), u.data_ptr(), gout.data_ptr(), gD.data_ptr(),
+                                             work.data_ptr(), nbytes, K, Np, F, _stream_handle(dev))
+    _raise_on(st, "dg_volume_grad_d")
+    return gD
+
+
 def dg_volume_f32s(D, G, u, out=None):
     """FP32 storage, split-BF16 products: same contract as dg_volume with float32 tensors."""
     K, F, Np = _sizes(u, D)
@@ -239,9 +277,10 @@ def dg_stream_calibrate(src, dst, copies):
 
 
 class DGVolume(torch.autograd.Function):
-    """out = dg_volume(D, G, u) with gradients for u and G from the adjoint kernel.
+    """out = dg_volume(D, G, u) with gradients for u and G from the adjoint kernel
+    and, when D requires one, for D from dg_volume_grad_d.
 
-    Call as ``DGVolume.apply(u, G, D)``.  D receives no gradient.
+    Call as ``DGVolume.apply(u, G, D)``.
     """
 
     @staticmethod
@@ -255,10 +294,15 @@ class DGVolume(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gout):
         u, G, D = ctx.saved_tensors
-        gu, gG = dg_volume_adjoint(D, G, u, gout.contiguous())
+        gout = gout.contiguous()
+        gu = gG = gD = None
+        if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
+            gu, gG = dg_volume_adjoint(D, G, u, gout)
+        if ctx.needs_input_grad[2]:
+            gD = dg_volume_grad_d(G, u, gout)
         return (gu if ctx.needs_input_grad[0] else None,
                 gG if ctx.needs_input_grad[1] else None,
-                None)
+                gD)
 
 
 def volume(u, G, D):

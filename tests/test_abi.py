@@ -32,7 +32,7 @@ def lib():
 
 def test_header_declares_the_boundary():
     names = _declared_functions()
-    for required in ("dg_volume", "dg_volume_adjoint", "dg_volume_f32s", "dg_strerror",
+    for required in ("dg_volume", "dg_volume_adjoint", "dg_volume_grad_d", "dg_volume_f32s", "dg_strerror",
                      "dg_supported_np", "dg_abi_version"):
         assert required in names
 
@@ -84,6 +84,37 @@ def test_adjoint_validation(lib):
         assert f(*ptrs, 5, 56, 3, None) == dgvol.DG_EINVAL
         ptrs[i] = FAKE + 4
         assert f(*ptrs, 5, 56, 3, None) == dgvol.DG_EINVAL
+
+
+def test_grad_d_workspace_and_validation(lib):
+    ws = dgvol.grad_d_workspace_bytes
+    # one partial sum per 32 columns, at most 512, each 3 Np^2 doubles
+    assert ws(0, 35, 5) == 0
+    assert ws(1, 35, 1) == 3 * 35 * 35 * 8
+    assert ws(32, 20, 1) == 3 * 20 * 20 * 8
+    assert ws(33, 20, 1) == 2 * 3 * 20 * 20 * 8
+    assert ws(11, 4, 3) == 2 * 3 * 4 * 4 * 8
+    assert ws(512 * 32, 56, 1) == 512 * 3 * 56 * 56 * 8
+    assert ws(1 << 20, 120, 5) == 512 * 3 * 120 * 120 * 8
+    n = ctypes.c_uint64(0)
+    assert lib.dg_volume_grad_d_workspace(10, 36, 1, ctypes.byref(n)) == dgvol.DG_EUNSUPPORTED
+    assert lib.dg_volume_grad_d_workspace(-1, 35, 1, ctypes.byref(n)) == dgvol.DG_EINVAL
+    assert lib.dg_volume_grad_d_workspace(10, 35, 0, ctypes.byref(n)) == dgvol.DG_EINVAL
+    assert lib.dg_volume_grad_d_workspace(10, 35, 1, None) == dgvol.DG_EINVAL
+    f = lib.dg_volume_grad_d
+    need = ws(100, 35, 3)
+    assert f(FAKE, FAKE, FAKE, FAKE, FAKE, need, -1, 35, 3, None) == dgvol.DG_EINVAL
+    assert f(FAKE, FAKE, FAKE, FAKE, FAKE, need, 100, 35, 0, None) == dgvol.DG_EINVAL
+    assert f(FAKE, FAKE, FAKE, FAKE, FAKE, need, 100, 34, 3, None) == dgvol.DG_EUNSUPPORTED
+    assert f(FAKE, FAKE, FAKE, FAKE, FAKE, need - 8, 100, 35, 3, None) == dgvol.DG_EINVAL
+    for i in range(5):
+        ptrs = [FAKE] * 5
+        ptrs[i] = None
+        assert f(*ptrs, need, 100, 35, 3, None) == dgvol.DG_EINVAL
+        ptrs[i] = FAKE + 4
+        assert f(*ptrs, need, 100, 35, 3, None) == dgvol.DG_EINVAL
+    # K == 0 still writes gD (zeros), so it needs gD, but nothing else
+    assert f(FAKE, FAKE, FAKE, None, FAKE, 0, 0, 35, 3, None) == dgvol.DG_EINVAL
 
 
 def test_python_binding_rejects_cpu_tensors():

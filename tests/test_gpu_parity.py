@@ -181,6 +181,82 @@ def test_adjoint_workload5_full_size_sampled():
     _check_adjoint(D, G[idx], u[idx], gout_s, host(gu[it]), host(gG[it]))
 
 
+# ------------------------------------------------------------------ cotangent of D
+
+def _check_grad_d(G, u, gout, gD):
+    """Per direction a: normwise and condition-scaled (the same sum over |G|, |u|, |gout|)."""
+    ref = oracle.volume_grad_d(G, u, gout)
+    cond = oracle.volume_grad_d(np.abs(G), np.abs(u), np.abs(gout))
+    check_planes(gD, ref, cond, what="gD")
+
+
+@pytest.mark.parametrize("N", range(1, 8))
+@pytest.mark.parametrize("F", [1, 3, 5, 17])
+def test_grad_d_orders_and_fields(N, F):
+    K = 131  # 131 F columns: several 32-column chunks and a ragged tail
+    _say(f"grad_d N={N} K={K} F={F}")
+    D, G, u = make_case(N, K, F, 900 + 10 * N + F, "normal")
+    gout = np.random.default_rng(N * 31 + F).standard_normal((3, K, F, oracle.num_nodes(N)))
+    gD = dgvol.dg_volume_grad_d(dev(G), dev(u), dev(gout))
+    _check_grad_d(G, u, gout, host(gD))
+
+
+@pytest.mark.parametrize("N", [1, 4, 5, 7])
+def test_grad_d_many_parts(N):
+    """More chunks than partial sums (563 chunks into 512 parts of one or two chunks)."""
+    K, F = 6000, 3
+    _say(f"grad_d many parts N={N} K={K} F={F}")
+    D, G, u = make_case(N, K, F, 950 + N)
+    gout = np.random.default_rng(951 + N).standard_normal((3, K, F, oracle.num_nodes(N)))
+    gD = dgvol.dg_volume_grad_d(dev(G), dev(u), dev(gout))
+    _check_grad_d(G, u, gout, host(gD))
+
+
+@pytest.mark.parametrize("K,F", [(1, 1), (2, 3), (1, 40), (0, 2)])
+def test_grad_d_small_and_empty(K, F):
+    for N in (1, 3, 7):
+        _say(f"grad_d small N={N} K={K} F={F}")
+        Np = oracle.num_nodes(N)
+        D, G, u = make_case(N, max(K, 1), F, 960 + K + F)
+        G, u = G[:K], u[:K]
+        gout = np.random.default_rng(961).standard_normal((3, K, F, Np))
+        gD = torch.full((3, Np, Np), float("nan"), dtype=torch.float64, device="cuda")
+        dgvol.dg_volume_grad_d(dev(G), dev(u), dev(gout), gD=gD)
+        _check_grad_d(G, u, gout, host(gD))
+        if K == 0:
+            assert np.all(host(gD) == 0.0)
+
+
+def test_grad_d_deterministic_and_workspace():
+    """Bitwise reproducible; stale workspace contents do not matter; a short workspace is refused."""
+    N, K, F = 4, 5000, 5
+    _say(f"grad_d determinism N={N} K={K} F={F}")
+    D, G, u = make_case(N, K, F, 970)
+    gout = np.random.default_rng(971).standard_normal((3, K, F, 35))
+    Gd, ud, gd = dev(G), dev(u), dev(gout)
+    need = dgvol.grad_d_workspace_bytes(K, 35, F)
+    work = torch.full((need // 8,), float("nan"), dtype=torch.float64, device="cuda")
+    a = host(dgvol.dg_volume_grad_d(Gd, ud, gd, work=work))
+    b = host(dgvol.dg_volume_grad_d(Gd, ud, gd))
+    assert np.array_equal(a, b)
+    _check_grad_d(G, u, gout, a)
+    with pytest.raises(dgvol.DGVolError):
+        dgvol.dg_volume_grad_d(Gd, ud, gd, work=work[: need // 8 - 1])
+
+
+def test_grad_d_workload5_full_size():
+    """Order 5, K=2^19, F=3, gout = 2 out (loss = sum(out^2)): every entry of gD
+    against the oracle's full reduction over 1.5 M columns."""
+    N, K, F = 5, 1 << 19, 3
+    _say(f"grad_d workload5 N={N} K={K} F={F}")
+    D = oracle.derivative_matrices(N)
+    G = oracle.geometric_factors(synth.tet_vertices(K, synth.mesh_seed(5)))
+    u = synth.fields(K, F, 56, synth.field_seed(5), "uniform")
+    gout = 2.0 * oracle.volume(D, G, u)
+    gD = dgvol.dg_volume_grad_d(dev(G), dev(u), dev(gout))
+    _check_grad_d(G, u, gout, host(gD))
+
+
 # ------------------------------------------------------------------ autograd
 
 def test_autograd_matches_oracle_and_finite_differences():
@@ -197,6 +273,7 @@ def test_autograd_matches_oracle_and_finite_differences():
     gu, gG = host(ut.grad), host(Gt.grad)
     ref_out = oracle.volume(D, G, u)
     _check_adjoint(D, G, u, 2.0 * ref_out, gu, gG)
+    assert Dd.grad is None  # D was not marked as requiring a gradient
 
     def loss(uu, GG):
         return float((dgvol.dg_volume(Dd, dev(GG), dev(uu)) ** 2).sum())
@@ -229,6 +306,36 @@ def test_torch_gradcheck():
     ut = dev(u).requires_grad_(True)
     Gt = dev(G).requires_grad_(True)
     assert torch.autograd.gradcheck(dgvol.DGVolume.apply, (ut, Gt, dev(D)), eps=1e-6, atol=1e-8, rtol=1e-6)
+    Dt = dev(D).requires_grad_(True)
+    assert torch.autograd.gradcheck(dgvol.DGVolume.apply, (ut, Gt, Dt), eps=1e-6, atol=1e-8, rtol=1e-6)
+
+
+def test_autograd_gradient_of_d():
+    """D marked as requiring a gradient: loss = sum(out^2) on 64 order-4 elements;
+    gD against the oracle (1e-12) and central differences in entries of D (1e-6)."""
+    N, K, F = 4, 64, 3
+    _say(f"autograd D N={N} K={K} F={F}")
+    D, G, u = make_case(N, K, F, 810)
+    Dt = dev(D).requires_grad_(True)
+    out = dgvol.volume(dev(u), dev(G), Dt)
+    (out ** 2).sum().backward()
+    gD = host(Dt.grad)
+    _check_grad_d(G, u, 2.0 * oracle.volume(D, G, u), gD)
+    Gd, ud = dev(G), dev(u)
+    rng = np.random.default_rng(811)
+    h = 1e-6
+    fd, an = [], []
+    for _ in range(18):
+        ix = (int(rng.integers(0, 3)), int(rng.integers(0, 35)), int(rng.integers(0, 35)))
+        Dp, Dm = D.copy(), D.copy()
+        Dp[ix] += h
+        Dm[ix] -= h
+        lp = float((dgvol.dg_volume(dev(Dp), Gd, ud) ** 2).sum())
+        lm = float((dgvol.dg_volume(dev(Dm), Gd, ud) ** 2).sum())
+        fd.append((lp - lm) / (2 * h))
+        an.append(gD[ix])
+    fd, an = np.array(fd), np.array(an)
+    assert np.abs(fd - an).max() <= 1e-6 * np.abs(an).max()
 
 
 # ------------------------------------------------------------------ split-BF16 form
