@@ -465,9 +465,21 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
 template <int NP>
 constexpr bool bf16_table_fits() { return bf16_table_entries<NP>() * 32 <= 96 * 1024; }
 
+// Tiles per wave iteration of the split-BF16 staged body: FP32 words halve the
+// bytes of a tile, so more tiles per iteration than in FP64 are needed to keep
+// enough bytes in flight.
+template <int NP>
+constexpr int f32s_tpi() { return NP <= 4 ? 8 : (NP <= 20 ? 4 : (NP <= 35 ? 2 : 1)); }
+
+template <int NP>
+constexpr int f32s_wave_floats() {
+  constexpr int TPI = f32s_tpi<NP>();
+  return TPI * 16 * NP + (TPI > 1 ? TPI * 16 * 9 : 0);
+}
+
 template <int NP, int WPB>
 constexpr int fwd_f32s_staged_lds() {
-  return (bf16_table_fits<NP>() ? 2 * bf16_table_entries<NP>() * 16 : 0) + WPB * 16 * NP * 4;
+  return (bf16_table_fits<NP>() ? 2 * bf16_table_entries<NP>() * 16 : 0) + WPB * f32s_wave_floats<NP>() * 4;
 }
 
 typedef float f32x2 __attribute__((ext_vector_type(2)));
@@ -479,8 +491,8 @@ __host__ __device__ inline bool f32_pairs_ok(const FwdArgs<float>& p) {
 }
 
 template <int NP, int WPB>
-__device__ __forceinline__ void fwd_f32s_staged_body(const FwdArgs<float>& p, uint32_t bid, uint32_t nblk,
-                                                     char* lds) {
+__device__ __forceinline__ void fwd_f32s_staged_single(const FwdArgs<float>& p, uint32_t bid, uint32_t nblk,
+                                                       char* lds) {
   using Sh = Shape<NP>;
   constexpr bool ALDS = bf16_table_fits<NP>();
   constexpr int NTE = ALDS ? bf16_table_entries<NP>() : 0;
@@ -615,6 +627,190 @@ __device__ __forceinline__ void fwd_f32s_staged_body(const FwdArgs<float>& p, ui
     }
     if (t + stride < p.ntiles) load_raw(t + stride);
   }
+}
+
+// Several tiles per iteration (FP32 words; see fwd_f64_staged_multi): a wave
+// takes TPI consecutive tiles, one contiguous run of u and of each plane (moved
+// as float pairs when aligned), and the geometric factors of their elements
+// as one run.
+template <int NP, int WPB>
+__device__ __forceinline__ void fwd_f32s_staged_multi(const FwdArgs<float>& p, uint32_t bid, uint32_t nblk,
+                                                      char* lds) {
+  using Sh = Shape<NP>;
+  constexpr int TPI = f32s_tpi<NP>();
+  constexpr bool ALDS = bf16_table_fits<NP>();
+  constexpr int NTE = ALDS ? bf16_table_entries<NP>() : 0;
+  constexpr int TILE = 16 * NP;
+  constexpr int RUN = TPI * TILE;  // even
+  constexpr int NRAW = (RUN + WAVE - 1) / WAVE;
+  constexpr int NPAIR = (RUN / 2 + WAVE - 1) / WAVE;
+  constexpr int NREG = NRAW > 2 * NPAIR ? NRAW : 2 * NPAIR;
+  constexpr int GW = TPI * 16 * 9;
+  constexpr int NGR = (GW + WAVE - 1) / WAVE;
+  Bf16x8Bits* ahi = reinterpret_cast<Bf16x8Bits*>(lds);
+  Bf16x8Bits* alo = ahi + NTE;
+  if constexpr (ALDS) {
+    for (int e = threadIdx.x; e < NTE; e += WAVE * WPB) {
+      const int ts = e >> 6;
+      Bf16x8Bits h, l;
+      afrag_bf16<NP>(p.D, ts / Sh::KS16, ts % Sh::KS16, e & 63, h, l);
+      ahi[e] = h;
+      alo[e] = l;
+    }
+    __syncthreads();
+  }
+  const bool pairs = f32_pairs_ok(p);
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const uint32_t wave = threadIdx.x >> 6;
+  float* su = reinterpret_cast<float*>(lds + 2 * NTE * 16) + wave * f32s_wave_floats<NP>();
+  float* sg = su + RUN;
+  const uint32_t nrun = (p.ntiles + TPI - 1) / TPI;
+  const uint32_t stride = nblk * WPB;
+  uint32_t t = bid * WPB + wave;
+  float raw[NREG], graw[NGR];
+  auto run_elems = [&](uint32_t tt, uint32_t& e0, int& ng) __attribute__((always_inline)) {
+    const uint32_t c0 = tt * (16 * TPI);
+    const uint32_t c1 = min(c0 + 16 * TPI, p.ncols) - 1;
+    e0 = c0 / p.F;
+    ng = (int)(c1 / p.F - e0 + 1) * 9;
+  };
+  auto load_run = [&](uint32_t tt) __attribute__((always_inline)) {
+    const uint32_t c0 = tt * (16 * TPI);
+    const float* __restrict__ src = p.u + (int64_t)c0 * NP;
+    const int cnt = (int)min(16u * TPI, p.ncols - c0) * NP;
+    if (pairs && cnt == RUN) {
+#pragma unroll
+      for (int q = 0; q < NPAIR; ++q) {
+        const int x = lane + WAVE * q;
+        if (x < RUN / 2) {
+          const f32x2 v = reinterpret_cast<const f32x2*>(src)[x];
+          raw[2 * q] = v[0];
+          raw[2 * q + 1] = v[1];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NREG; ++q) {
+        const int x = lane + WAVE * q;
+        raw[q] = x < cnt ? src[x] : 0.0f;
+      }
+    }
+    uint32_t e0;
+    int ng;
+    run_elems(tt, e0, ng);
+    const float* __restrict__ gsrc = p.G + (int64_t)e0 * 9;
+#pragma unroll
+    for (int q = 0; q < NGR; ++q) {
+      const int x = lane + WAVE * q;
+      graw[q] = x < ng ? gsrc[x] : 0.0f;
+    }
+  };
+  if (t < nrun) load_run(t);
+  for (; t < nrun; t += stride) {
+    const uint32_t col0 = t * (16 * TPI);
+    const int cnt = (int)min(16u * TPI, p.ncols - col0) * NP;
+    const bool whole = pairs && cnt == RUN;
+    uint32_t e0;
+    int ng;
+    run_elems(t, e0, ng);
+    if (whole) {
+#pragma unroll
+      for (int q = 0; q < NPAIR; ++q) {
+        const int x = lane + WAVE * q;
+        if (x < RUN / 2) reinterpret_cast<f32x2*>(su)[x] = f32x2{raw[2 * q], raw[2 * q + 1]};
+      }
+    } else {
+#pragma unroll
+      for (int q = 0; q < NRAW; ++q) {
+        const int x = lane + WAVE * q;
+        if (x < RUN) su[x] = raw[q];
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NGR; ++q) {
+      const int x = lane + WAVE * q;
+      if (x < GW) sg[x] = graw[q];
+    }
+    wave_sync();
+    f32x4 acc[TPI][Sh::MT];
+#pragma unroll
+    for (int r = 0; r < TPI; ++r) {
+      Bf16x8Bits bh[Sh::KS16], bl[Sh::KS16];
+#pragma unroll
+      for (int s = 0; s < Sh::KS16; ++s) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+          const int j = 32 * s + 8 * g + e;
+          split_bf16(j < NP ? su[r * TILE + n * NP + j] : 0.0f, bh[s].v[e], bl[s].v[e]);
+        }
+      }
+#pragma unroll
+      for (int T = 0; T < Sh::MT; ++T) acc[r][T] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int s = 0; s < Sh::KS16; ++s) {
+#pragma unroll
+        for (int T = 0; T < Sh::MT; ++T) {
+          Bf16x8Bits ah, al;
+          if constexpr (ALDS) {
+            ah = ahi[(T * Sh::KS16 + s) * WAVE + lane];
+            al = alo[(T * Sh::KS16 + s) * WAVE + lane];
+          } else {
+            afrag_bf16<NP>(p.D, T, s, lane, ah, al);
+          }
+          acc[r][T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al), as_bf16x8(bh[s]), acc[r][T], 0, 0, 0);
+          acc[r][T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bl[s]), acc[r][T], 0, 0, 0);
+          acc[r][T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bh[s]), acc[r][T], 0, 0, 0);
+          __builtin_amdgcn_sched_barrier(0);
+        }
+      }
+    }
+    wave_sync();
+    if (t + stride < nrun) load_run(t + stride);
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+#pragma unroll
+      for (int r = 0; r < TPI; ++r) {
+        const uint32_t col = col0 + 16 * r + n;
+        const int ge = col < p.ncols ? (int)(col / p.F - e0) * 9 : 0;
+        const float g0 = sg[ge + bb], g1 = sg[ge + 3 + bb], g2 = sg[ge + 6 + bb];
+#pragma unroll
+        for (int tau = 0; tau < Sh::TRIP; ++tau) {
+          const int i = 4 * tau + g;
+          const int s0 = 3 * tau;
+          const float v = g0 * acc[r][s0 >> 2][s0 & 3] + g1 * acc[r][(s0 + 1) >> 2][(s0 + 1) & 3] +
+                          g2 * acc[r][(s0 + 2) >> 2][(s0 + 2) & 3];
+          if (i < NP) su[r * TILE + n * NP + i] = v;
+        }
+      }
+      wave_sync();
+      float* __restrict__ ob = p.out + bb * p.plane + (int64_t)col0 * NP;
+      if (whole) {
+#pragma unroll
+        for (int q = 0; q < NPAIR; ++q) {
+          const int x = lane + WAVE * q;
+          if (x < RUN / 2) reinterpret_cast<f32x2*>(ob)[x] = reinterpret_cast<const f32x2*>(su)[x];
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < NRAW; ++q) {
+          const int x = lane + WAVE * q;
+          if (x < cnt) ob[x] = su[x];
+        }
+      }
+      wave_sync();
+    }
+    (void)ng;
+  }
+}
+
+template <int NP, int WPB>
+__device__ __forceinline__ void fwd_f32s_staged_body(const FwdArgs<float>& p, uint32_t bid, uint32_t nblk,
+                                                     char* lds) {
+  if constexpr (f32s_tpi<NP>() > 1)
+    fwd_f32s_staged_multi<NP, WPB>(p, bid, nblk, lds);
+  else
+    fwd_f32s_staged_single<NP, WPB>(p, bid, nblk, lds);
 }
 
 // ------------------------------------------------------------------ split-BF16 chunk-register

@@ -4,19 +4,22 @@
 // planes the cotangent of D is a sum over every element column c = (k, f):
 //   W_a[c][i]   = sum_b G[k][3a+b] gout[b][c][i]
 //   gD[a][i][j] = sum_c W_a[c][i] u[c][j]
-// which is the contraction W_a^T u with the element columns as its (long)
-// reduction dimension: a GEMM of shape [Np x ncols] . [ncols x Np] per
-// direction.  It runs on the FP64 matrix cores with the columns as the MFMA
-// k dimension:
+// Stacking the three directions, rows r = a Np + i, this is ONE contraction
+//   gD[r][j] = sum_c W[c][r] u[c][j]          ([3Np x ncols] . [ncols x Np])
+// whose reduction dimension is the (long) column axis.  It runs on the FP64
+// matrix cores with the columns as the MFMA k dimension:
 //
-//   * the columns are split into npart contiguous ranges of 32-column chunks
-//     (staged 16 or 32 columns per step); one workgroup (two at the highest
-//     order, each with half of the tiles) owns one range and keeps the
-//     3 x ceil(Np/16)^2 output tiles of its partial sum in accumulators,
-//     spread over its waves;
-//   * per chunk the workgroup stages u[c][:] and W_a[c][:] (formed from gout
-//     and G while staging) in LDS, row-major per column, and every wave feeds
-//     its tiles' MFMAs from there: A[i][c] = W_a[c][i], B[c][j] = u[c][j];
+//   * the 3Np stacked rows form ceil(3Np/16) row tiles and the Np columns
+//     ceil(Np/16) column blocks (stacking wastes less of a 16-row tile than
+//     padding every direction separately);
+//   * the columns are split into npart contiguous ranges; one workgroup owns
+//     one range (at the two highest orders NSPLIT workgroups, each with a
+//     share of the row tiles) and keeps its output tiles in accumulators
+//     spread over its waves; with fewer tiles than waves the waves also split
+//     the k steps and add their partial tiles at the end in a fixed order;
+//   * per step the workgroup stages u[c][:] and W[c][rows] in LDS, row-major
+//     per column; each thread stages a fixed column, so it needs the
+//     geometric factors of one element only;
 //   * each workgroup writes its partial gD to work[part]; a second kernel adds
 //     the partials in a fixed order.
 //
@@ -28,31 +31,39 @@
 
 namespace dgvol {
 
-// Upper bound on the number of partial sums (workgroups of the first pass).
-constexpr uint32_t GD_MAXPART = 512;
-// Element columns staged per step: a multiple of the MFMA k (4) and a divisor
-// of GD_CHUNK_MAX, which fixes the partition into chunks for every order.
-constexpr int GD_CHUNK_MAX = 32;
+// Columns per partition unit; every staging step (16..128 columns) divides it.
+constexpr int GD_UNIT = 128;
+constexpr int GD_WPB = 8;
+
+// Upper bound on the number of partial sums (a function of Np only).
+__host__ __device__ constexpr uint32_t gd_maxpart(int np) { return np <= 35 ? 1024u : 512u; }
+
+// Row stride in LDS: an odd multiple of 16 doubles, so the 16-lane row
+// segments of an MFMA operand read start 128 bytes apart modulo 256 and two of
+// them never share banks.
+constexpr int gd_ld(int n16) { return (n16 / 16) % 2 == 1 ? n16 : n16 + 16; }
 
 template <int NP>
 struct GdShape {
-  static constexpr int CH = NP >= 84 ? 16 : 32;           // columns per step
-  static constexpr int NB = (NP + 15) / 16;               // 16-row blocks of one matrix
-  static constexpr int NPAD = 16 * NB;
-  static constexpr int LD = (NB & 1) ? NPAD : NPAD + 16;  // LDS row stride: rows 4 apart never share banks
-  static constexpr int WPB = 8;
-  static constexpr int NTH = WAVE * WPB;
-  static constexpr int NT = 3 * NB * NB;                   // 16x16 output tiles
-  // Workgroups per column range, each owning 1/NSPLIT of the tiles: at the
-  // highest order the accumulators of all tiles do not fit one workgroup's
-  // registers, and that order is bound by the matrix cores, so reading its
-  // columns twice costs little.
-  static constexpr int NSPLIT = NP >= 120 ? 2 : 1;
-  static constexpr int TPS = (NT + NSPLIT - 1) / NSPLIT;   // tiles per workgroup
-  static constexpr int TPW = (TPS + WPB - 1) / WPB;        // tiles per wave
-  static constexpr int NXE = CH * NP;                      // staged values per plane per step
-  static constexpr int NX = (NXE + NTH - 1) / NTH;         // per thread
-  static constexpr int LDS_DOUBLES = 4 * CH * LD + CH * 9;
+  static constexpr int NTH = WAVE * GD_WPB;
+  static constexpr int NB = (NP + 15) / 16;            // column blocks (j)
+  static constexpr int RT = (3 * NP + 15) / 16;        // row tiles (stacked r = a Np + i)
+  static constexpr int NSPLIT = NP >= 120 ? 4 : (NP >= 84 ? 2 : 1);
+  static constexpr int RTS = (RT + NSPLIT - 1) / NSPLIT;  // row tiles per workgroup
+  static constexpr int NTW = RTS * NB;                  // output tiles per workgroup
+  static constexpr int KSPLIT = NTW >= GD_WPB ? 1 : (NTW == 1 ? 8 : (NTW == 2 ? 4 : 2));
+  static constexpr int SLOTS = NTW * KSPLIT;            // (tile, k share) pairs
+  static constexpr int TPW = (SLOTS + GD_WPB - 1) / GD_WPB;
+  static constexpr int CH = NP <= 4 ? 128 : (NP <= 10 ? 64 : (NP <= 35 ? 32 : 16));
+  static constexpr int TPC = NTH / CH;                  // threads staging one column
+  static constexpr int NXU = (NP + TPC - 1) / TPC;      // values per thread and plane
+  static constexpr int LDU = gd_ld(16 * NB);
+  static constexpr int LDW = gd_ld(16 * RTS);
+  static constexpr int STAGE_DOUBLES = CH * (LDU + LDW);
+  static constexpr int RED_DOUBLES = KSPLIT > 1 ? SLOTS * 256 : 0;
+  static constexpr int LDS_DOUBLES = STAGE_DOUBLES > RED_DOUBLES ? STAGE_DOUBLES : RED_DOUBLES;
+  static_assert(GD_UNIT % CH == 0 && CH % 4 == 0, "staging step");
+  static_assert((CH / 4) % KSPLIT == 0, "k steps split evenly");
 };
 
 struct GdArgs {
@@ -63,117 +74,148 @@ struct GdArgs {
   uint32_t ncols;    // K * F
   uint32_t F;
   int64_t plane;     // K * F * Np
-  uint32_t nchunks;  // ceil(ncols / GD_CHUNK_MAX)
+  uint32_t nunits;   // ceil(ncols / GD_UNIT)
   uint32_t npart;
 };
 
+// Two workgroups per CU (at most 128 registers a lane) so that one stages
+// while the other multiplies.
 template <int NP>
-__global__ __launch_bounds__(GdShape<NP>::NTH) void gd_partial_kernel(GdArgs p) {
+__global__ __launch_bounds__(GdShape<NP>::NTH) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void gd_partial_kernel(GdArgs p) {
   using S = GdShape<NP>;
   constexpr int CH = S::CH;
-  constexpr int SUB = GD_CHUNK_MAX / CH;  // steps per chunk
+  constexpr int SUB = GD_UNIT / CH;  // steps per partition unit
   __shared__ double lds[S::LDS_DOUBLES];
-  double* ul = lds;                        // [CH][LD]      u[c][j]
-  double* wl = lds + CH * S::LD;           // [3][CH][LD]   W_a[c][i]
-  double* gl = lds + 4 * CH * S::LD;       // [CH][9]       G row of column c
+  double* ul = lds;                // [CH][LDU]  u[c][j]
+  double* wl = lds + CH * S::LDU;  // [CH][LDW]  W[c][r - r0]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const uint32_t part = blockIdx.x / S::NSPLIT;
-  const int t_first = (blockIdx.x % S::NSPLIT) * S::TPS + wave * S::TPW;  // this wave's first tile
-  const int t_stop = min((int)(blockIdx.x % S::NSPLIT + 1) * S::TPS, S::NT);
-  // this part's chunks, as steps of CH columns
-  const uint32_t ch_begin = (uint32_t)((uint64_t)part * p.nchunks / p.npart) * SUB;
-  const uint32_t ch_end = (uint32_t)((uint64_t)(part + 1) * p.nchunks / p.npart) * SUB;
+  // Workgroups of one column range sit on one XCD (workgroups are dealt to
+  // the 8 XCDs in turn), so the NSPLIT reads of a column hit one L2.
+  uint32_t part, split;
+  if constexpr (S::NSPLIT == 1) {
+    part = blockIdx.x;
+    split = 0;
+  } else {
+    const uint32_t j = blockIdx.x >> 3;
+    split = j % S::NSPLIT;
+    part = (j / S::NSPLIT) * 8 + (blockIdx.x & 7);
+  }
+  if (part >= p.npart) return;
+  const uint32_t st_begin = (uint32_t)((uint64_t)part * p.nunits / p.npart) * SUB;
+  const uint32_t st_end = (uint32_t)((uint64_t)(part + 1) * p.nunits / p.npart) * SUB;
+  const int r0 = (int)split * S::RTS * 16;  // first stacked row of this workgroup
+  const int r1 = min(r0 + S::RTS * 16, 3 * NP);
 
-  // Rows are padded from Np to LD; the pad only feeds output rows and columns
-  // beyond Np, which are never stored, but keep it finite.
-  constexpr int PADW = S::LD - NP;
-  for (int x = tid; x < 4 * CH * PADW; x += S::NTH) lds[(x / PADW) * S::LD + NP + x % PADW] = 0.0;
+  // Pad entries (columns Np.. of u, rows r1-r0.. of W) feed only outputs that
+  // are never stored; keep them finite.
+  for (int x = tid; x < S::STAGE_DOUBLES; x += S::NTH) lds[x] = 0.0;
+  __syncthreads();
 
-  double ru[S::NX], rg0[S::NX], rg1[S::NX], rg2[S::NX];
-  double rG = 0.0;
-  auto load = [&](uint32_t ch) __attribute__((always_inline)) {
-    const uint32_t col0 = ch * CH;
-    const uint32_t cnt = col0 < p.ncols ? min((uint32_t)CH, p.ncols - col0) * NP : 0u;
-    const int64_t base = (int64_t)col0 * NP;
+  // this thread's column within a step and its first row
+  const int cc = tid / S::TPC;
+  const int rr = tid % S::TPC;
+  double ru[S::NXU], rg0[S::NXU], rg1[S::NXU], rg2[S::NXU], rG[9];
+  auto load = [&](uint32_t st) __attribute__((always_inline)) {
+    const uint32_t col = st * CH + cc;
+    const bool v = col < p.ncols;
+    const int64_t base = (int64_t)col * NP;
 #pragma unroll
-    for (int q = 0; q < S::NX; ++q) {
-      const uint32_t x = tid + S::NTH * q;
-      const bool v = x < cnt;
-      ru[q] = v ? p.u[base + x] : 0.0;
-      rg0[q] = v ? p.gout[base + x] : 0.0;
-      rg1[q] = v ? p.gout[p.plane + base + x] : 0.0;
-      rg2[q] = v ? p.gout[2 * p.plane + base + x] : 0.0;
+    for (int q = 0; q < S::NXU; ++q) {
+      const int i = rr + S::TPC * q;
+      const bool ok = v && i < NP;
+      ru[q] = ok ? p.u[base + i] : 0.0;
+      rg0[q] = ok ? p.gout[base + i] : 0.0;
+      rg1[q] = ok ? p.gout[p.plane + base + i] : 0.0;
+      rg2[q] = ok ? p.gout[2 * p.plane + base + i] : 0.0;
     }
-    if (tid < CH * 9) {
-      const uint32_t col = col0 + tid / 9;
-      rG = col < p.ncols ? p.G[(int64_t)(col / p.F) * 9 + tid % 9] : 0.0;
-    }
+    const int64_t gb = (int64_t)(v ? col / p.F : 0u) * 9;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) rG[m] = v ? p.G[gb + m] : 0.0;
   };
 
   f64x4 acc[S::TPW];
 #pragma unroll
   for (int t = 0; t < S::TPW; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  if (ch_begin < ch_end) load(ch_begin);
-  for (uint32_t ch = ch_begin; ch < ch_end; ++ch) {
-    __syncthreads();  // the previous chunk's products are done with the LDS
+  if (st_begin < st_end) load(st_begin);
+  for (uint32_t st = st_begin; st < st_end; ++st) {
+    __syncthreads();  // the previous step's products are done with the LDS
 #pragma unroll
-    for (int q = 0; q < S::NX; ++q) {
-      const int x = tid + S::NTH * q;
-      if (x < S::NXE) ul[(x / NP) * S::LD + x % NP] = ru[q];
-    }
-    if (tid < CH * 9) gl[tid] = rG;
-    __syncthreads();
+    for (int q = 0; q < S::NXU; ++q) {
+      const int i = rr + S::TPC * q;
+      if (i < NP) {
+        ul[cc * S::LDU + i] = ru[q];
 #pragma unroll
-    for (int q = 0; q < S::NX; ++q) {
-      const int x = tid + S::NTH * q;
-      if (x < S::NXE) {
-        const int c = x / NP, i = x % NP;
-        const double* g = gl + 9 * c;
-#pragma unroll
-        for (int a = 0; a < 3; ++a)
-          wl[(a * CH + c) * S::LD + i] = g[3 * a] * rg0[q] + g[3 * a + 1] * rg1[q] + g[3 * a + 2] * rg2[q];
-      }
-    }
-    __syncthreads();
-    if (ch + 1 < ch_end) load(ch + 1);
-#pragma unroll
-    for (int t = 0; t < S::TPW; ++t) {
-      const int T = t_first + t;
-      if (T < t_stop) {
-        const int a = T / (S::NB * S::NB);
-        const int ib = (T / S::NB) % S::NB;
-        const int jb = T % S::NB;
-        const double* wa = wl + a * CH * S::LD + ib * 16 + (lane & 15);
-        const double* ub = ul + jb * 16 + (lane & 15);
-#pragma unroll
-        for (int kk = 0; kk < CH / 4; ++kk) {
-          const int c = 4 * kk + (lane >> 4);
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[c * S::LD], ub[c * S::LD], acc[t], 0, 0, 0);
+        for (int a = 0; a < 3; ++a) {
+          const int r = a * NP + i;
+          if (r >= r0 && r < r1)
+            wl[cc * S::LDW + (r - r0)] = rG[3 * a] * rg0[q] + rG[3 * a + 1] * rg1[q] + rG[3 * a + 2] * rg2[q];
         }
       }
-      // one tile's operands at a time: keeps the LDS reads from being hoisted
-      // into registers for every tile at once
+    }
+    __syncthreads();
+    if (st + 1 < st_end) load(st + 1);
+#pragma unroll
+    for (int t = 0; t < S::TPW; ++t) {
+      const int slot = wave * S::TPW + t;
+      if (slot < S::SLOTS) {
+        const int T = slot / S::KSPLIT;
+        const int ks = slot % S::KSPLIT;
+        const int rt = T / S::NB;
+        const int jb = T % S::NB;
+        const double* wa = wl + rt * 16 + (lane & 15);
+        const double* ub = ul + jb * 16 + (lane & 15);
+#pragma unroll
+        for (int kk = ks; kk < CH / 4; kk += S::KSPLIT) {
+          const int c = 4 * kk + (lane >> 4);
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(wa[c * S::LDW], ub[c * S::LDU], acc[t], 0, 0, 0);
+        }
+      }
+      // one slot's operands at a time: keeps the LDS reads from being hoisted
+      // into registers for every slot at once
       __builtin_amdgcn_sched_barrier(0);
     }
   }
 
+  // Add the k shares of each tile (fixed order) and store the partial sum.
   double* w = p.work + (int64_t)part * 3 * NP * NP;
+  auto store_tile = [&](int T, const f64x4& v) __attribute__((always_inline)) {
+    const int rt = T / S::NB;
+    const int jb = T % S::NB;
+    const int j = jb * 16 + (lane & 15);
 #pragma unroll
-  for (int t = 0; t < S::TPW; ++t) {
-    const int T = t_first + t;
-    if (T < t_stop) {
-      const int a = T / (S::NB * S::NB);
-      const int ib = (T / S::NB) % S::NB;
-      const int jb = T % S::NB;
-      const int j = jb * 16 + (lane & 15);
+    for (int q = 0; q < 4; ++q) {
+      const int r = r0 + rt * 16 + 4 * q + (lane >> 4);
+      if (r < r1 && j < NP) w[(int64_t)r * NP + j] = v[q];
+    }
+  };
+  if constexpr (S::KSPLIT == 1) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int i = ib * 16 + 4 * q + (lane >> 4);
-        if (i < NP && j < NP) w[((int64_t)a * NP + i) * NP + j] = acc[t][q];
+    for (int t = 0; t < S::TPW; ++t) {
+      const int slot = wave * S::TPW + t;
+      if (slot < S::SLOTS) store_tile(slot, acc[t]);
+    }
+  } else {
+    __syncthreads();  // staging buffers are reused for the k shares
+#pragma unroll
+    for (int t = 0; t < S::TPW; ++t) {
+      const int slot = wave * S::TPW + t;
+      if (slot < S::SLOTS) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) lds[(slot * 4 + q) * WAVE + lane] = acc[t][q];
       }
+    }
+    __syncthreads();
+    for (int T = wave; T < S::NTW; T += GD_WPB) {
+      f64x4 v = f64x4{0.0, 0.0, 0.0, 0.0};
+      for (int ks = 0; ks < S::KSPLIT; ++ks) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[q] += lds[((T * S::KSPLIT + ks) * 4 + q) * WAVE + lane];
+      }
+      store_tile(T, v);
     }
   }
 }

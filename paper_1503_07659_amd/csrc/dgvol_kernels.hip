@@ -283,8 +283,10 @@ static int lds_bytes(int form, int Np, int body) {
 
 // 16-column tiles one workgroup processes per step of its loop.
 static inline uint32_t tiles_per_block(int form, int Np, int body) {
-  if (body == BODY_STAGED)
-    return form == DG_FORM_F64 ? FWD_WPB * (Np <= 4 ? staged_tpi<4>() : Np <= 20 ? staged_tpi<20>() : 1) : FWD_WPB;
+  if (body == BODY_STAGED) {
+    if (form == DG_FORM_F64) return FWD_WPB * (Np <= 4 ? staged_tpi<4>() : Np <= 20 ? staged_tpi<20>() : 1);
+    return FWD_WPB * (Np <= 4 ? f32s_tpi<4>() : Np <= 20 ? f32s_tpi<20>() : Np <= 35 ? f32s_tpi<35>() : 1);
+  }
   if (form != DG_FORM_F64) return chunk_tpw<4, 4>();
   return Np >= 120 ? chunk_tpw<120, 8>() : chunk_tpw<4, 8>();
 }
@@ -347,21 +349,23 @@ static dg_status launch_adj_f64(const double* D, const double* G, const double* 
 
 // Partial sums of the D cotangent: a pure function of the problem size, so
 // the result does not depend on the device.
-static uint32_t gd_parts(int64_t K, int32_t F) {
-  const uint32_t nchunks = ceil_div((uint64_t)K * (uint64_t)F, GD_CHUNK_MAX);
-  return std::min<uint32_t>(nchunks, GD_MAXPART);
+static uint32_t gd_parts(int64_t K, int32_t Np, int32_t F) {
+  const uint32_t nunits = ceil_div((uint64_t)K * (uint64_t)F, GD_UNIT);
+  return std::min<uint32_t>(nunits, gd_maxpart(Np));
 }
 
 template <int NP>
 static dg_status launch_gd_f64(const double* G, const double* u, const double* gout, double* gD, double* work,
                                int64_t K, int32_t F, hipStream_t stream) {
+  using S = GdShape<NP>;
   const uint64_t ncols = (uint64_t)K * (uint64_t)F;
-  const uint32_t npart = gd_parts(K, F);
+  const uint32_t npart = gd_parts(K, NP, F);
   if (npart > 0) {
-    const GdArgs p{G, u, gout, work, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP,
-                   ceil_div(ncols, GD_CHUNK_MAX), npart};
-    hipLaunchKernelGGL(gd_partial_kernel<NP>, dim3(npart * GdShape<NP>::NSPLIT), dim3(GdShape<NP>::NTH), 0, stream,
-                       p);
+    const GdArgs p{G, u, gout, work, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP, ceil_div(ncols, GD_UNIT),
+                   npart};
+    // with NSPLIT > 1 the grid is rounded up to whole groups of 8 ranges (one per XCD)
+    const uint32_t grid = S::NSPLIT == 1 ? npart : ceil_div(npart, 8) * 8 * S::NSPLIT;
+    hipLaunchKernelGGL(gd_partial_kernel<NP>, dim3(grid), dim3(S::NTH), 0, stream, p);
   }
   const uint32_t n = 3u * NP * NP;
   hipLaunchKernelGGL(gd_reduce_kernel, dim3(ceil_div(n, 64)), dim3(64 * GD_RED_PG), 0, stream, work, gD, npart,
@@ -489,7 +493,7 @@ dg_status dg_volume_grad_d_workspace(int64_t K, int32_t Np, int32_t F, uint64_t*
   bool noop = false;
   const dg_status st = check_common(K, Np, F, &noop);
   if (st != DG_OK) return st;
-  *bytes = (uint64_t)gd_parts(K, F) * 3u * (uint64_t)Np * (uint64_t)Np * sizeof(double);
+  *bytes = (uint64_t)gd_parts(K, Np, F) * 3u * (uint64_t)Np * (uint64_t)Np * sizeof(double);
   return DG_OK;
 }
 

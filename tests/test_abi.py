@@ -88,13 +88,14 @@ def test_adjoint_validation(lib):
 
 def test_grad_d_workspace_and_validation(lib):
     ws = dgvol.grad_d_workspace_bytes
-    # one partial sum per 32 columns, at most 512, each 3 Np^2 doubles
+    # one partial sum per 128 columns, at most 1024 (Np <= 35) or 512, each 3 Np^2 doubles
     assert ws(0, 35, 5) == 0
     assert ws(1, 35, 1) == 3 * 35 * 35 * 8
-    assert ws(32, 20, 1) == 3 * 20 * 20 * 8
-    assert ws(33, 20, 1) == 2 * 3 * 20 * 20 * 8
-    assert ws(11, 4, 3) == 2 * 3 * 4 * 4 * 8
-    assert ws(512 * 32, 56, 1) == 512 * 3 * 56 * 56 * 8
+    assert ws(128, 20, 1) == 3 * 20 * 20 * 8
+    assert ws(129, 20, 1) == 2 * 3 * 20 * 20 * 8
+    assert ws(43, 4, 3) == 2 * 3 * 4 * 4 * 8
+    assert ws(1024 * 128 + 1, 35, 1) == 1024 * 3 * 35 * 35 * 8
+    assert ws(512 * 128, 56, 1) == 512 * 3 * 56 * 56 * 8
     assert ws(1 << 20, 120, 5) == 512 * 3 * 120 * 120 * 8
     n = ctypes.c_uint64(0)
     assert lib.dg_volume_grad_d_workspace(10, 36, 1, ctypes.byref(n)) == dgvol.DG_EUNSUPPORTED

@@ -203,8 +203,9 @@ def test_grad_d_orders_and_fields(N, F):
 
 @pytest.mark.parametrize("N", [1, 4, 5, 7])
 def test_grad_d_many_parts(N):
-    """More chunks than partial sums (563 chunks into 512 parts of one or two chunks)."""
-    K, F = 6000, 3
+    """More 128-column units than partial sums (1172 units into 1024 or 512 parts of
+    one to three units each)."""
+    K, F = 50000, 3
     _say(f"grad_d many parts N={N} K={K} F={F}")
     D, G, u = make_case(N, K, F, 950 + N)
     gout = np.random.default_rng(951 + N).standard_normal((3, K, F, oracle.num_nodes(N)))
