@@ -64,14 +64,18 @@ def adj_flops_per_element(F, Np):
     return F * Np * (12 * Np + 33)
 
 
+# Sources the forward kernel is built from (its body, layout and device helpers, and
+# the translation unit that instantiates and launches it).
+FWD_KERNEL_SOURCES = ("dgvol_device.hpp", "dgvol_forward.hpp", "dgvol_kernels.hip", "dgvol_layout.hpp")
+
+
 def kernel_source_sha():
-    """SHA-256 over every kernel source file (sorted by name)."""
+    """SHA-256 over the forward kernel's source files (in the order above)."""
     h = hashlib.sha256()
-    for name in sorted(os.listdir(KERNEL_SRC_DIR)):
-        if name.endswith((".hip", ".hpp")):
-            h.update(name.encode())
-            with open(os.path.join(KERNEL_SRC_DIR, name), "rb") as fh:
-                h.update(fh.read())
+    for name in FWD_KERNEL_SOURCES:
+        h.update(name.encode())
+        with open(os.path.join(KERNEL_SRC_DIR, name), "rb") as fh:
+            h.update(fh.read())
     return h.hexdigest()
 
 
@@ -370,14 +374,22 @@ def main():
         ka, kf = float(np.mean(pera)), float(np.mean(perf))
         d5 = K5 * F5 * Np5
         fl_f, fl_a = K5 * fwd_flops_per_element(F5, Np5), K5 * adj_flops_per_element(F5, Np5)
+        # cotangent of D for the same cotangent (both kernels of the call are timed)
+        gD5 = torch.empty_like(D5)
+        wk5 = torch.empty(dgvol.grad_d_workspace_bytes(K5, Np5, F5), dtype=torch.uint8, device=dev)
+        msd, perd = time_launches(lambda: dgvol.dg_volume_grad_d(G5, u5, g5, gD=gD5, work=wk5), 20, 3, torch)
+        kd = float(np.mean(perd))
         forms["fp64_order5_K524288_F3"] = {
+            "grad_D_GDOF/s": round(d5 / (msd * 1e-3) / 1e9, 3), "grad_D_call_ms": round(kd, 5),
+            "grad_D_hbm_frac": round(K5 * fwd_bytes_per_element(F5, Np5) / (kd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "grad_D_fp64_frac": round(fl_f / (kd * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
             "forward_GDOF/s": round(d5 / (msf * 1e-3) / 1e9, 3), "forward_kernel_ms": round(kf, 5),
             "forward_fp64_frac": round(fl_f / (kf * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
             "forward_hbm_frac": round(K5 * fwd_bytes_per_element(F5, Np5) / (kf * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "adjoint_GDOF/s": round(d5 / (msa * 1e-3) / 1e9, 3), "adjoint_kernel_ms": round(ka, 5),
             "adjoint_fp64_frac": round(fl_a / (ka * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
             "adjoint_hbm_frac": round(K5 * adj_bytes_per_element(F5, Np5) / (ka * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
-        del D5, G5, u5, o5, g5, gu5, gG5
+        del D5, G5, u5, o5, g5, gu5, gG5, gD5, wk5
         torch.cuda.empty_cache()
         forms["mixed_orders1to7_F3"] = mixed_orders(torch, dev)
         rec["forms"] = forms

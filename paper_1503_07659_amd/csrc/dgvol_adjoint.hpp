@@ -206,7 +206,7 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   const uint32_t wave = threadIdx.x >> 6;
   double* stg = stg_all + wave * 16 * LD;
   double* red = red_all + wave * 16 * 9;
-  double* gks = gks_all + wave * 16 * 9;  // geometric factors of the wave's 16 columns
+  double* gks = gks_all + wave * 16 * 9;  // geometric factors of the tile's (at most 16) elements
   // per-lane LDS offsets: forward rows by s & 3, transposed rows by sp & 3
   int fo[4], tb[4];
 #pragma unroll
@@ -216,16 +216,26 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   }
   const uint32_t stride = gridDim.x * WPB;
   uint32_t t = blockIdx.x * WPB + wave;
-  double raw[NRAW];
-  auto load_raw = [&](uint32_t tt) {
+  // u of the tile and the geometric factors of its elements (one contiguous
+  // run of G), loaded one tile ahead
+  constexpr int NGR = (16 * 9 + WAVE - 1) / WAVE;
+  double raw[NRAW], graw[NGR];
+  auto load_raw = [&](uint32_t tt) __attribute__((always_inline)) {
     const uint32_t kk0 = tt * E;
+    const uint32_t ne = min(E, K - kk0);
     const double* __restrict__ src = u + (int64_t)kk0 * F * NP;
-    const int cnt = (int)(min(E, K - kk0) * F) * NP;
+    const int cnt = (int)(ne * F) * NP;
 #pragma unroll
     for (int q = 0; q < NRAW; ++q) {
       const int x = lane + WAVE * q;
       const double v = src[min(x, cnt - 1)];
       raw[q] = x < cnt ? v : 0.0;
+    }
+    const double* __restrict__ gsrc = G + (int64_t)kk0 * 9;
+#pragma unroll
+    for (int q = 0; q < NGR; ++q) {
+      const int x = lane + WAVE * q;
+      graw[q] = x < (int)ne * 9 ? gsrc[x] : 0.0;
     }
   };
   if (t < ntiles) load_raw(t);
@@ -240,15 +250,16 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
       const int x = lane + WAVE * q;
       if (NRAW * WAVE == TILE || x < TILE) stg[(x / NP) * LD + (x % NP)] = raw[q];
     }
+#pragma unroll
+    for (int q = 0; q < NGR; ++q) {
+      const int x = lane + WAVE * q;
+      if (x < 16 * 9) gks[x] = graw[q];
+    }
     wave_sync();
     const bool valid = (uint32_t)n < ncolt;
     const uint32_t e = valid ? (uint32_t)n / F : 0u;
     const uint32_t col = col0 + (valid ? n : 0);
-    if (g == 0) {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) gks[n * 9 + c] = G[(int64_t)(k0 + e) * 9 + c];
-    }
-    wave_sync();
+    const double* ge = gks + e * 9;  // geometric factors of this column's element
     const double* __restrict__ goc = gout + (int64_t)col * NP;
     f64x4 accj[Sh::MTJ];
 #pragma unroll
@@ -301,8 +312,7 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
             const double R = acc[loc >> 2][loc & 3];
 #pragma unroll
             for (int bb = 0; bb < 3; ++bb) P[3 * a + bb] += go[x][bb] * R;
-            W[loc] = gks[n * 9 + 3 * a] * go[x][0] + gks[n * 9 + 3 * a + 1] * go[x][1] +
-                     gks[n * 9 + 3 * a + 2] * go[x][2];
+            W[loc] = ge[3 * a] * go[x][0] + ge[3 * a + 1] * go[x][1] + ge[3 * a + 2] * go[x][2];
           }
         }
       }
