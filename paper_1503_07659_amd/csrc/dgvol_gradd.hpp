@@ -54,7 +54,11 @@ struct GdShape {
   static constexpr int KSPLIT = NTW >= GD_WPB ? 1 : (NTW == 1 ? 8 : (NTW == 2 ? 4 : 2));
   static constexpr int SLOTS = NTW * KSPLIT;            // (tile, k share) pairs
   static constexpr int TPW = (SLOTS + GD_WPB - 1) / GD_WPB;
-  static constexpr int CH = NP <= 4 ? 128 : (NP <= 10 ? 64 : (NP <= 35 ? 32 : 16));
+  static constexpr int CH = NP <= 4 ? 128 : (NP <= 10 ? 64 : (NP <= 56 ? 32 : 16));
+  // Register prefetch of the next step (measured): it pays at the low orders,
+  // whose steps are short; at Np = 35, 56 the registers it holds are worth
+  // more than the latency it hides.
+  static constexpr bool PREFETCH = !(NP == 35 || NP == 56);
   static constexpr int TPC = NTH / CH;                  // threads staging one column
   static constexpr int NXU = (NP + TPC - 1) / TPC;      // values per thread and plane
   static constexpr int LDU = gd_ld(16 * NB);
@@ -140,8 +144,11 @@ void gd_partial_kernel(GdArgs p) {
 #pragma unroll
   for (int t = 0; t < S::TPW; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
 
-  if (st_begin < st_end) load(st_begin);
+  if constexpr (S::PREFETCH) {
+    if (st_begin < st_end) load(st_begin);
+  }
   for (uint32_t st = st_begin; st < st_end; ++st) {
+    if constexpr (!S::PREFETCH) load(st);
     __syncthreads();  // the previous step's products are done with the LDS
 #pragma unroll
     for (int q = 0; q < S::NXU; ++q) {
@@ -157,7 +164,9 @@ void gd_partial_kernel(GdArgs p) {
       }
     }
     __syncthreads();
-    if (st + 1 < st_end) load(st + 1);
+    if constexpr (S::PREFETCH) {
+      if (st + 1 < st_end) load(st + 1);
+    }
 #pragma unroll
     for (int t = 0; t < S::TPW; ++t) {
       const int slot = wave * S::TPW + t;
