@@ -299,9 +299,6 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
         }
         __builtin_amdgcn_sched_barrier(0);
       }
-      double W[12];
-#pragma unroll
-      for (int x = 0; x < 12; ++x) W[x] = 0.0;
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
         const int tau = 4 * ch + x;
@@ -312,7 +309,6 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
             const double R = acc[loc >> 2][loc & 3];
 #pragma unroll
             for (int bb = 0; bb < 3; ++bb) P[3 * a + bb] += go[x][bb] * R;
-            W[loc] = ge[3 * a] * go[x][0] + ge[3 * a + 1] * go[x][1] + ge[3 * a + 2] * go[x][2];
           }
         }
       }
@@ -320,10 +316,12 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
       for (int sl = 0; sl < 12; ++sl) {
         const int sp = 12 * ch + sl;
         if (sp < Sh::SLOTS) {
+          const int x = sl / 3, a = sl % 3;
+          const double wv = ge[3 * a] * go[x][0] + ge[3 * a + 1] * go[x][1] + ge[3 * a + 2] * go[x][2];
 #pragma unroll
           for (int tj = 0; tj < Sh::MTJ; ++tj)
             accj[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[((sp >> 2) * KS + 4 * tj) * WAVE + tb[sp & 3]],
-                                                            W[sl], accj[tj], 0, 0, 0);
+                                                            wv, accj[tj], 0, 0, 0);
           __builtin_amdgcn_sched_barrier(0);
         }
       }
