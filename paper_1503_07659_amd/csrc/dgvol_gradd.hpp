@@ -54,7 +54,7 @@ struct GdShape {
   static constexpr int KSPLIT = NTW >= GD_WPB ? 1 : (NTW == 1 ? 8 : (NTW == 2 ? 4 : 2));
   static constexpr int SLOTS = NTW * KSPLIT;            // (tile, k share) pairs
   static constexpr int TPW = (SLOTS + GD_WPB - 1) / GD_WPB;
-  static constexpr int CH = NP <= 4 ? 128 : (NP <= 10 ? 64 : (NP <= 56 ? 32 : 16));
+  static constexpr int CH = NP <= 10 ? 128 : (NP <= 20 ? 64 : (NP <= 56 ? 32 : 16));
   // Register prefetch of the next step (measured): it pays at the low orders,
   // whose steps are short; at Np = 35, 56 the registers it holds are worth
   // more than the latency it hides.
