@@ -64,9 +64,9 @@ def adj_flops_per_element(F, Np):
     return F * Np * (12 * Np + 33)
 
 
-# Sources the forward kernel is built from (its body, layout and device helpers, and
-# the translation unit that instantiates and launches it).
-FWD_KERNEL_SOURCES = ("dgvol_device.hpp", "dgvol_forward.hpp", "dgvol_kernels.hip", "dgvol_layout.hpp")
+# Device sources the forward kernel is built from: its body, layout and device
+# helpers, and the header that defines the entry kernel.
+FWD_KERNEL_SOURCES = ("dgvol_device.hpp", "dgvol_forward.hpp", "dgvol_global.hpp", "dgvol_layout.hpp")
 
 
 def kernel_source_sha():

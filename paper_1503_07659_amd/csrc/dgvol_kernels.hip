@@ -1,11 +1,13 @@
-// HIP kernels of the DG volume derivative for gfx950 (MI355X) and the C ABI.
+// Host side of the DG volume derivative library for gfx950 (MI355X): launches and the C ABI.
 //
 // Forward:  out_b[i] = sum_a G[3a+b] (D_a u)[i]   for every (element, field) column.
 // Adjoint:  gu = sum_a D_a^T W_a with W_a = sum_b G[3a+b] gout_b;
 //           gG[3a+b] = sum_{f,i} gout_b[i] (D_a u)[i].
 // Definitions, layouts and error behaviour are documented in include/dgvol.h;
 // the forward data-movement schemes in dgvol_forward.hpp, the adjoint in
-// dgvol_adjoint.hpp, the register layout of the products in dgvol_layout.hpp.
+// dgvol_adjoint.hpp, the D cotangent in dgvol_gradd.hpp, the register layout
+// of the products in dgvol_layout.hpp, the entry kernels in dgvol_global.hpp.
+// This file holds the host side: launch configuration, validation, the ABI.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -17,159 +19,11 @@
 #include "dgvol_adjoint.hpp"
 #include "dgvol_device.hpp"
 #include "dgvol_forward.hpp"
+#include "dgvol_global.hpp"
 #include "dgvol_gradd.hpp"
 #include "dgvol_layout.hpp"
 
 namespace dgvol {
-
-constexpr int FWD_WPB = 8;   // waves per workgroup of every forward launch
-constexpr int ADJ_WPB = 8;
-
-// body ids (DG_BODY_STAGED, DG_BODY_CHUNKREG in dgvol.h)
-constexpr int BODY_STAGED = DG_BODY_STAGED;
-constexpr int BODY_CHUNKREG = DG_BODY_CHUNKREG;
-
-template <int NP>
-constexpr bool f64_staged_ok() { return fwd_f64_staged_lds<NP, FWD_WPB>() <= 160 * 1024; }
-
-template <int NP, int BODY>
-constexpr int f64_lds() {
-  return BODY == BODY_STAGED ? fwd_f64_staged_lds<NP, FWD_WPB>() : fwd_f64_chunkreg_lds<NP, FWD_WPB>();
-}
-template <int NP, int BODY>
-constexpr int f32s_lds() {
-  return BODY == BODY_STAGED ? fwd_f32s_staged_lds<NP, FWD_WPB>() : fwd_f32s_chunkreg_lds<NP, FWD_WPB>();
-}
-
-// ------------------------------------------------------------------ single-group kernels
-
-template <int NP, int BODY>
-__global__ __launch_bounds__(WAVE* FWD_WPB) void fwd_f64_kernel(FwdArgs<double> p) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  if constexpr (BODY == BODY_STAGED)
-    fwd_f64_staged_body<NP, FWD_WPB>(p, blockIdx.x, gridDim.x, lds);
-  else
-    fwd_f64_chunkreg_body<NP, FWD_WPB>(p, blockIdx.x, gridDim.x, lds);
-}
-
-template <int NP, int BODY>
-__global__ __launch_bounds__(WAVE* FWD_WPB) void fwd_f32s_kernel(FwdArgs<float> p) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  if constexpr (BODY == BODY_STAGED)
-    fwd_f32s_staged_body<NP, FWD_WPB>(p, blockIdx.x, gridDim.x, lds);
-  else
-    fwd_f32s_chunkreg_body<NP, FWD_WPB>(p, blockIdx.x, gridDim.x, lds);
-}
-
-// ------------------------------------------------------------------ mixed-order batched kernels
-//
-// One persistent launch over up to MAX_GROUPS element groups of different
-// orders.  Workgroups are split between groups on the host in proportion to
-// each group's cost (a static partition: deterministic, no device-side queue,
-// nothing to reset between launches, so the launch can be captured in a
-// graph).  Block b belongs to the group g with wg_begin[g] <= b < wg_begin[g+1]
-// and runs that group's body with its rank and count within the group.
-
-constexpr int MAX_GROUPS = DG_MAX_GROUPS;
-
-struct GroupDev {
-  int32_t Np;
-  int32_t body;
-  uint32_t ncols;
-  uint32_t ntiles;
-  int64_t plane;
-  const void* D;
-  const void* G;
-  const void* u;
-  void* out;
-};
-
-struct BatchArgs {
-  GroupDev g[MAX_GROUPS];
-  uint32_t wg_begin[MAX_GROUPS + 1];
-  int32_t ngroups;
-  uint32_t F;
-};
-
-template <typename T>
-__device__ __forceinline__ FwdArgs<T> group_args(const GroupDev& gd, uint32_t F) {
-  return FwdArgs<T>{static_cast<const T*>(gd.D), static_cast<const T*>(gd.G), static_cast<const T*>(gd.u),
-                    static_cast<T*>(gd.out), gd.ncols, F, gd.plane, gd.ntiles};
-}
-
-__device__ __forceinline__ int find_group(const BatchArgs& a) {
-  int gi = 0;
-  while (gi + 1 < a.ngroups && blockIdx.x >= a.wg_begin[gi + 1]) ++gi;
-  return gi;
-}
-
-#define DGVOL_CASE64(NPV) \
-  case NPV * 2 + BODY_CHUNKREG: fwd_f64_chunkreg_body<NPV, FWD_WPB>(p, bid, nblk, lds); break;
-
-__global__ __launch_bounds__(WAVE* FWD_WPB) void batched_f64_kernel(BatchArgs a) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  const int gi = find_group(a);
-  const GroupDev& gd = a.g[gi];
-  const uint32_t bid = blockIdx.x - a.wg_begin[gi];
-  const uint32_t nblk = a.wg_begin[gi + 1] - a.wg_begin[gi];
-  const FwdArgs<double> p = group_args<double>(gd, a.F);
-  switch (gd.Np * 2 + gd.body) {
-    case 4 * 2 + BODY_STAGED: fwd_f64_staged_body<4, FWD_WPB>(p, bid, nblk, lds); break;
-    case 10 * 2 + BODY_STAGED: fwd_f64_staged_body<10, FWD_WPB>(p, bid, nblk, lds); break;
-    case 20 * 2 + BODY_STAGED: fwd_f64_staged_body<20, FWD_WPB>(p, bid, nblk, lds); break;
-    case 35 * 2 + BODY_STAGED: fwd_f64_staged_body<35, FWD_WPB>(p, bid, nblk, lds); break;
-    case 56 * 2 + BODY_STAGED: fwd_f64_staged_body<56, FWD_WPB>(p, bid, nblk, lds); break;
-    DGVOL_CASE64(4)
-    DGVOL_CASE64(10)
-    DGVOL_CASE64(20)
-    DGVOL_CASE64(35)
-    DGVOL_CASE64(56)
-    DGVOL_CASE64(84)
-    DGVOL_CASE64(120)
-    default: break;
-  }
-}
-#undef DGVOL_CASE64
-
-#define DGVOL_CASE32(NPV)                                                                   \
-  case NPV * 2 + BODY_STAGED: fwd_f32s_staged_body<NPV, FWD_WPB>(p, bid, nblk, lds); break; \
-  case NPV * 2 + BODY_CHUNKREG: fwd_f32s_chunkreg_body<NPV, FWD_WPB>(p, bid, nblk, lds); break;
-
-__global__ __launch_bounds__(WAVE* FWD_WPB) void batched_f32s_kernel(BatchArgs a) {
-  extern __shared__ __attribute__((aligned(16))) char lds[];
-  const int gi = find_group(a);
-  const GroupDev& gd = a.g[gi];
-  const uint32_t bid = blockIdx.x - a.wg_begin[gi];
-  const uint32_t nblk = a.wg_begin[gi + 1] - a.wg_begin[gi];
-  const FwdArgs<float> p = group_args<float>(gd, a.F);
-  switch (gd.Np * 2 + gd.body) {
-    DGVOL_CASE32(4)
-    DGVOL_CASE32(10)
-    DGVOL_CASE32(20)
-    DGVOL_CASE32(35)
-    DGVOL_CASE32(56)
-    DGVOL_CASE32(84)
-    DGVOL_CASE32(120)
-    default: break;
-  }
-}
-#undef DGVOL_CASE32
-
-// ------------------------------------------------------------------ stream calibration
-//
-// Reads n doubles once and writes `copies` scaled copies of them (dst[c*n + i]
-// = (c + 1) * src[i]) with contiguous 8-byte accesses.  With copies = 1 this is
-// a plain copy of known size (the scale of the hardware byte counters); with
-// copies = 3 it moves bytes in the forward kernel's 1 : 3 read : write mix with
-// no other work (the practical streaming ceiling for that mix).
-__global__ __launch_bounds__(256) void stream_kernel(const double* __restrict__ src, double* __restrict__ dst,
-                                                     int64_t n, int32_t copies) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const double v = src[i];
-    for (int32_t c = 0; c < copies; ++c) dst[c * n + i] = (double)(c + 1) * v;
-  }
-}
 
 // ------------------------------------------------------------------ launch helpers
 
@@ -373,15 +227,28 @@ static dg_status launch_gd_f64(const double* G, const double* u, const double* g
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
 
-// Roofline estimate of one 16-column tile (seconds), used to split workgroups
-// between groups when the caller gives no measured cost.
+// Estimate of one 16-column tile (seconds), used to split workgroups between
+// groups when the caller gives no measured cost: the spec roofline time
+// (8 TB/s, spec matrix peak) divided by the fraction of it that the order's
+// default body reached in single-order launches on MI355X (large K, F = 3).
+// Only the ratios between groups matter.
 static double tile_cost_estimate(int form, int Np, uint32_t F) {
   const double word = form == DG_FORM_F64 ? 8.0 : 4.0;
   const double bytes = 16.0 * word * (4.0 * Np + 9.0 / F);
   const double flops = 16.0 * Np * (6.0 * Np + 15.0);
-  const double bw = 5.3e12;                                          // measured streaming rate, 1:3 mix
+  const double bw = 8.0e12;
   const double peak = form == DG_FORM_F64 ? 78.6e12 : 2.5e15 / 3.0;  // three BF16 passes
-  return std::max(bytes / bw, flops / peak);
+  double eff;
+  switch (Np) {
+    case 4: eff = form == DG_FORM_F64 ? 0.64 : 0.31; break;
+    case 10: eff = form == DG_FORM_F64 ? 0.61 : 0.38; break;
+    case 20: eff = form == DG_FORM_F64 ? 0.59 : 0.53; break;
+    case 35: eff = form == DG_FORM_F64 ? 0.60 : 0.55; break;
+    case 56: eff = form == DG_FORM_F64 ? 0.45 : 0.55; break;
+    case 84: eff = form == DG_FORM_F64 ? 0.38 : 0.49; break;
+    default: eff = form == DG_FORM_F64 ? 0.53 : 0.20; break;  // Np = 120
+  }
+  return std::max(bytes / bw, flops / peak) / eff;
 }
 
 // ------------------------------------------------------------------ validation
