@@ -62,7 +62,9 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_kernel(
       f64x4 accj[Sh::MTJ];
 #pragma unroll
       for (int tj = 0; tj < Sh::MTJ; ++tj) accj[tj] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
+      // chunks in a loop, not unrolled: unrolled, the chunks' operands and W
+      // slots overflow the registers (kilobytes of spill at Np = 84)
+#pragma unroll 1
       for (int ch = 0; ch < Sh::NCHUNK; ++ch) {
         f64x4 acc[3];
 #pragma unroll
@@ -82,12 +84,13 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_kernel(
 #pragma unroll
         for (int x = 0; x < 12; ++x) W[x] = 0.0;
 #pragma unroll
-        for (int tau = 4 * ch; tau < 4 * ch + 4; ++tau) {
+        for (int xx = 0; xx < 4; ++xx) {
+          const int tau = 4 * ch + xx;
           if (tau < Sh::TRIP) {
             double R[3];
 #pragma unroll
             for (int a = 0; a < 3; ++a) {
-              const int loc = 3 * tau + a - 12 * ch;
+              const int loc = 3 * xx + a;
               R[a] = acc[loc >> 2][loc & 3];
             }
             const int i = 4 * tau + g;
@@ -100,7 +103,7 @@ __global__ __launch_bounds__(WAVE* WPB) void adj_f64_kernel(
             for (int a = 0; a < 3; ++a) {
 #pragma unroll
               for (int bb = 0; bb < 3; ++bb) P[3 * a + bb] += go[bb] * R[a];
-              W[3 * (tau - 4 * ch) + a] = gk[3 * a] * go[0] + gk[3 * a + 1] * go[1] + gk[3 * a + 2] * go[2];
+              W[3 * xx + a] = gk[3 * a] * go[0] + gk[3 * a + 1] * go[1] + gk[3 * a + 2] * go[2];
             }
           }
         }
