@@ -127,8 +127,17 @@ def cpu_baseline(D, G, u, min_seconds=10.0, max_reps=1000):
         el = time.perf_counter() - t0
         if el >= min_seconds or reps >= max_reps:
             break
+    cpu = "unknown"
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for ln in fh:
+                if ln.startswith("model name"):
+                    cpu = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": round(reps * K * F * Np / el / 1e9, 4), "unit": "GDOF/s",
-            "cores": oracle.num_threads(), "kind": "oracle",
+            "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu,
             "sample": f"first {K} of {WORKLOAD['K']} elements (order 4, F=5), {reps} pass(es) in {el:.1f} s"}
 
 
@@ -317,6 +326,12 @@ def main():
     ceil_gbs = 4 * n_u * 8 / (float(np.median(per_c)) * 1e-3) / 1e9
     _, per_1 = time_launches(lambda: dgvol.dg_stream_calibrate(ud.view(-1), out.view(-1)[:n_u], 1), 10, 2, torch)
     copy_gbs = 2 * n_u * 8 / (float(np.median(per_1)) * 1e-3) / 1e9
+    # attainable FP64 matrix-core rate: independent MFMA chains from registers
+    sink, _ = dgvol.dg_mfma_calibrate(10)
+    _, per_m = time_launches(lambda: dgvol.dg_mfma_calibrate(10000, sink=sink), 5, 1, torch)
+    cal_flops = dgvol.MFMA_CAL_BLOCKS * 4 * 10000 * 4 * 2048
+    mfma_tfs = cal_flops / (float(np.median(per_m)) * 1e-3) / 1e12
+    del sink
 
     rec = {
         "metric": METRIC,
@@ -340,7 +355,8 @@ def main():
                      "frac_of_measured_ceiling": round(achieved / ceil_gbs, 4),
                      "measured_copy_GBs": round(copy_gbs, 1),
                      "fp64_tflops": round(flops_launch / (kern_ms * 1e-3) / 1e12, 2),
-                     "fp64_frac": round(flops_launch / (kern_ms * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)},
+                     "fp64_frac": round(flops_launch / (kern_ms * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
+                     "measured_fp64_mfma_TFs": round(mfma_tfs, 2)},
     }
     del out
     torch.cuda.empty_cache()
@@ -388,6 +404,7 @@ def main():
             "forward_hbm_frac": round(K5 * fwd_bytes_per_element(F5, Np5) / (kf * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "adjoint_GDOF/s": round(d5 / (msa * 1e-3) / 1e9, 3), "adjoint_kernel_ms": round(ka, 5),
             "adjoint_fp64_frac": round(fl_a / (ka * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
+            "adjoint_frac_of_measured_mfma": round(fl_a / (ka * 1e-3) / 1e12 / mfma_tfs, 4),
             "adjoint_hbm_frac": round(K5 * adj_bytes_per_element(F5, Np5) / (ka * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del D5, G5, u5, o5, g5, gu5, gG5, gD5, wk5
         torch.cuda.empty_cache()

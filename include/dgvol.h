@@ -194,6 +194,18 @@ int32_t dg_default_body(int32_t form, int32_t Np);
  */
 dg_status dg_stream_calibrate(const double *src, double *dst, int64_t n, int32_t copies, void *stream);
 
+/*
+ * FP64 matrix-core calibration (not part of the DG computation).  Launches
+ * DG_MFMA_CAL_BLOCKS workgroups of 256 threads (4 waves); every wave issues
+ * `iters` rounds of 4 independent v_mfma_f64_16x16x4f64 (2048 flops each)
+ * from registers, i.e. DG_MFMA_CAL_BLOCKS * 4 * iters * 4 * 2048 flops in all,
+ * and writes one double per thread to sink[0 .. DG_MFMA_CAL_BLOCKS * 256).
+ * Timed by the caller, it gives the attainable FP64 matrix rate of the device.
+ * Errors: DG_EINVAL (null or misaligned sink, iters < 1), DG_ELAUNCH.
+ */
+#define DG_MFMA_CAL_BLOCKS 2048
+dg_status dg_mfma_calibrate(double *sink, int32_t iters, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

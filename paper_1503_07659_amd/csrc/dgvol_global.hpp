@@ -1,6 +1,6 @@
 // The __global__ entry kernels of the library: single-group forward kernels
-// (FP64, split-BF16), the mixed-order batched kernels and the bandwidth
-// calibration kernel, with the per-form LDS sizes their launches use.  The
+// (FP64, split-BF16), the mixed-order batched kernels and the bandwidth and
+// matrix-core calibration kernels, with the per-form LDS sizes their launches use.  The
 // adjoint and D-cotangent kernels live with their bodies (dgvol_adjoint.hpp,
 // dgvol_gradd.hpp); the host-side launch code and the C ABI are in
 // dgvol_kernels.hip.
@@ -164,6 +164,30 @@ __global__ __launch_bounds__(256) void stream_kernel(const double* __restrict__ 
     const double v = src[i];
     for (int32_t c = 0; c < copies; ++c) dst[c * n + i] = (double)(c + 1) * v;
   }
+}
+
+// ------------------------------------------------------------------ matrix-core calibration
+//
+// Every wave runs `iters` rounds of four independent accumulator chains of
+// v_mfma_f64_16x16x4f64 with register operands (no memory traffic in the
+// loop), then writes one sum per lane, so the work cannot be dropped.  The
+// operands change every round so no product is loop-invariant.
+__global__ __launch_bounds__(256) void mfma_cal_kernel(double* __restrict__ sink, int32_t iters) {
+  const int lane = threadIdx.x & 63;
+  double a = 1.0 + 1e-3 * lane, b = 1.0 - 1e-3 * lane;
+  f64x4 c0 = f64x4{0.0, 0.0, 0.0, 0.0}, c1 = c0, c2 = c0, c3 = c0;
+  for (int32_t it = 0; it < iters; ++it) {
+    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c0, 0, 0, 0);
+    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c1, 0, 0, 0);
+    c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, c2, 0, 0, 0);
+    c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, b, c3, 0, 0, 0);
+    a = a * 0.999 + 1e-4;
+    b = b * 0.999 + 2e-4;
+  }
+  double s = 0.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) s += c0[q] + c1[q] + c2[q] + c3[q];
+  sink[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
 }  // namespace dgvol

@@ -463,4 +463,10 @@ dg_status dg_stream_calibrate(const double* src, double* dst, int64_t n, int32_t
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
 
+dg_status dg_mfma_calibrate(double* sink, int32_t iters, void* stream) {
+  if (!sink || !aligned(sink, 8) || iters < 1) return DG_EINVAL;
+  hipLaunchKernelGGL(mfma_cal_kernel, dim3(DG_MFMA_CAL_BLOCKS), dim3(256), 0, (hipStream_t)stream, sink, iters);
+  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+}
+
 }  // extern "C"

@@ -80,6 +80,8 @@ def load_library(path=None):
     lib.dg_volume_f32s.restype = I32
     lib.dg_stream_calibrate.argtypes = [P, P, I64, I32, P]
     lib.dg_stream_calibrate.restype = I32
+    lib.dg_mfma_calibrate.argtypes = [P, I32, P]
+    lib.dg_mfma_calibrate.restype = I32
     lib.dg_volume_batched.argtypes = [ctypes.POINTER(DgGroup), I32, I32, I32, P]
     lib.dg_volume_batched.restype = I32
     lib.dg_body_available.argtypes = [I32, I32, I32]
@@ -274,6 +276,21 @@ def dg_stream_calibrate(src, dst, copies):
         st = load_library().dg_stream_calibrate(src.data_ptr(), dst.data_ptr(), n, copies, _stream_handle(dev))
     _raise_on(st, "dg_stream_calibrate")
     return dst
+
+
+MFMA_CAL_BLOCKS = 2048
+
+
+def dg_mfma_calibrate(iters, sink=None):
+    """Run the FP64 matrix-core calibration kernel; returns (sink, flops executed)."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if sink is None:
+        sink = torch.empty(MFMA_CAL_BLOCKS * 256, dtype=torch.float64, device=dev)
+    _check_tensor("sink", sink, torch.float64, (MFMA_CAL_BLOCKS * 256,))
+    with torch.cuda.device(sink.device):
+        st = load_library().dg_mfma_calibrate(sink.data_ptr(), int(iters), _stream_handle(sink.device))
+    _raise_on(st, "dg_mfma_calibrate")
+    return sink, MFMA_CAL_BLOCKS * 4 * int(iters) * 4 * 2048
 
 
 class DGVolume(torch.autograd.Function):

@@ -118,6 +118,12 @@ def test_grad_d_workspace_and_validation(lib):
     assert f(FAKE, FAKE, FAKE, None, FAKE, 0, 0, 35, 3, None) == dgvol.DG_EINVAL
 
 
+def test_mfma_calibrate_validation(lib):
+    assert lib.dg_mfma_calibrate(None, 10, None) == dgvol.DG_EINVAL
+    assert lib.dg_mfma_calibrate(FAKE + 4, 10, None) == dgvol.DG_EINVAL
+    assert lib.dg_mfma_calibrate(FAKE, 0, None) == dgvol.DG_EINVAL
+
+
 def test_python_binding_rejects_cpu_tensors():
     import torch
     u = torch.zeros((4, 1, 20), dtype=torch.float64)

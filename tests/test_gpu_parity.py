@@ -394,6 +394,24 @@ def test_stream_calibrate():
 
 # ------------------------------------------------------------------ mixed-order batched launch
 
+def test_mfma_calibrate():
+    """The matrix-core calibration runs, writes every sink entry, and reaches a
+    plausible fraction of the 78.6 TFLOP/s FP64 peak."""
+    _say("mfma calibrate")
+    sink = torch.full((dgvol.MFMA_CAL_BLOCKS * 256,), float("nan"), dtype=torch.float64, device="cuda")
+    dgvol.dg_mfma_calibrate(10, sink=sink)
+    torch.cuda.synchronize()
+    assert torch.isfinite(sink).all()
+    s = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    _, flops = dgvol.dg_mfma_calibrate(2000, sink=sink)
+    e1.record(s)
+    torch.cuda.synchronize()
+    tflops = flops / (e0.elapsed_time(e1) * 1e-3) / 1e12
+    assert 20.0 < tflops < 90.0, tflops
+
+
 def _mixed_case(sizes, F, form, seed):
     D, G, u = {}, {}, {}
     for N, K in sizes.items():
