@@ -170,19 +170,20 @@ __global__ __launch_bounds__(256) void stream_kernel(const double* __restrict__ 
 //
 // Every wave runs `iters` rounds of four independent accumulator chains of
 // v_mfma_f64_16x16x4f64 with register operands (no memory traffic in the
-// loop), then writes one sum per lane, so the work cannot be dropped.  The
-// operands change every round so no product is loop-invariant.
-__global__ __launch_bounds__(256) void mfma_cal_kernel(double* __restrict__ sink, int32_t iters) {
+// loop), then writes one sum per lane, so the work cannot be dropped.  Each
+// product depends on the previous one of its chain; the operands stay fixed
+// (rewriting a source register of an MFMA in flight would stall the issue).
+// Launched with 256 threads; the wider bound keeps the accumulators in VGPRs
+// (with a 256-thread bound the compiler moves them through AGPRs every round).
+__global__ __launch_bounds__(1024) void mfma_cal_kernel(double* __restrict__ sink, int32_t iters) {
   const int lane = threadIdx.x & 63;
-  double a = 1.0 + 1e-3 * lane, b = 1.0 - 1e-3 * lane;
+  const double a = 1.0 + 1e-3 * lane, b = 1.0 - 1e-3 * lane;
   f64x4 c0 = f64x4{0.0, 0.0, 0.0, 0.0}, c1 = c0, c2 = c0, c3 = c0;
   for (int32_t it = 0; it < iters; ++it) {
     c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c0, 0, 0, 0);
     c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c1, 0, 0, 0);
     c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, c2, 0, 0, 0);
     c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, b, c3, 0, 0, 0);
-    a = a * 0.999 + 1e-4;
-    b = b * 0.999 + 2e-4;
   }
   double s = 0.0;
 #pragma unroll
