@@ -1,0 +1,269 @@
+// Adjoint at the high orders (Np = 84, 120) in two chunk-register passes.
+//
+// At these orders D (170-345 KB in FP64) does not fit in LDS, so the single
+// staged adjoint cannot hold its operand table.  As in the forward
+// chunk-register body, the 8 waves of a workgroup each keep a share of D in
+// registers for the whole launch, and the workgroup stages the columns it
+// works on in LDS:
+//
+//   pass A (gu):  gu[c][j] = sum_{a,i} D[a][i][j] W_a[c][i],
+//                 W_a[c][i] = sum_b G[k][3a+b] gout_b[c][i]   (k = c / F).
+//     Wave w < ceil(Np/16) owns output rows j = 16w..16w+15 and keeps the A
+//     operands of the transposed product (k = slot sp: direction sp % 3,
+//     nodes 4 (sp/3) + lane group) for all 3 ceil(Np/4) k-steps.  Per 16
+//     columns the workgroup forms W from gout and G (each thread stages a fixed
+//     column, so it needs one element's geometric factors) into LDS, each wave
+//     runs its k-steps, and gu leaves through an LDS tile as contiguous runs.
+//   pass B (gG):  gG[k][3a+b] = sum_f sum_i gout_b[c][i] (D_a u)[c][i].
+//     Wave w < NCHUNK keeps the A operands of forward output chunk w (as the
+//     forward chunk-register body), recomputes D u for its 4 node triples from
+//     u staged in LDS, and reduces it with gout at its lanes' nodes.  Tiles are
+//     whole elements (16/F of them, or one element in ceil(F/16) sub-tiles when
+//     F > 16) so every element's sums finish inside one workgroup; the partial
+//     sums are added in a fixed order (lane groups, then sub-tiles, then
+//     waves, then the element's columns), so gG is reproducible bit for bit.
+//
+// gout is read twice (once per pass), u once; the matrix work equals the
+// single-pass adjoint's.
+#pragma once
+
+#include "dgvol_device.hpp"
+#include "dgvol_layout.hpp"
+
+namespace dgvol {
+
+constexpr int ADJCR_WPB = 8;
+
+// ------------------------------------------------------------------ pass A: gu
+
+template <int NP>
+struct AdjCrA {
+  static constexpr int NTH = WAVE * ADJCR_WPB;
+  static constexpr int KT = Shape<NP>::SLOTS;         // k-steps (slots) of the transposed product
+  static constexpr int MTJ = Shape<NP>::MTJ;          // output tiles (waves with work)
+  static constexpr int LDW = 3 * NP + 1;              // odd row stride of the W stage
+  static constexpr int TPC = NTH / 16;                // threads staging one column
+  static constexpr int NX = (NP + TPC - 1) / TPC;     // nodes per thread
+  static_assert(MTJ <= ADJCR_WPB, "one wave per output tile");
+};
+
+template <int NP>
+__global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double* __restrict__ D,
+                                                                  const double* __restrict__ G,
+                                                                  const double* __restrict__ gout,
+                                                                  double* __restrict__ gu, uint32_t ncols, uint32_t F,
+                                                                  int64_t plane, uint32_t ntiles) {
+  using S = AdjCrA<NP>;
+  __shared__ double ws[16 * S::LDW];  // W[c][a Np + i]
+  __shared__ double ostg[16 * NP];    // gu tile, column-major runs
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int w = tid >> 6;
+  const bool mma = w < S::MTJ;
+  double areg[S::KT];
+#pragma unroll
+  for (int sp = 0; sp < S::KT; ++sp) areg[sp] = mma ? afragT_f64<NP>(D, w, sp, lane) : 0.0;
+
+  // staging: thread (cc, rr) owns column cc of the tile and nodes rr + TPC x
+  const int cc = tid / S::TPC, rr = tid % S::TPC;
+  double r0[S::NX], r1[S::NX], r2[S::NX], rG[9];
+  auto load = [&](uint32_t t) __attribute__((always_inline)) {
+    const uint32_t col = t * 16 + cc;
+    const bool v = col < ncols;
+    const int64_t base = (int64_t)col * NP;
+#pragma unroll
+    for (int x = 0; x < S::NX; ++x) {
+      const int i = rr + S::TPC * x;
+      const bool ok = v && i < NP;
+      r0[x] = ok ? gout[base + i] : 0.0;
+      r1[x] = ok ? gout[plane + base + i] : 0.0;
+      r2[x] = ok ? gout[2 * plane + base + i] : 0.0;
+    }
+    const int64_t gb = (int64_t)(v ? col / F : 0u) * 9;
+#pragma unroll
+    for (int m = 0; m < 9; ++m) rG[m] = v ? G[gb + m] : 0.0;
+  };
+  uint32_t t = blockIdx.x;
+  if (t < ntiles) load(t);
+  for (; t < ntiles; t += gridDim.x) {
+    const uint32_t col0 = t * 16;
+    const int cnt = (int)min(16u, ncols - col0) * NP;
+#pragma unroll
+    for (int x = 0; x < S::NX; ++x) {
+      const int i = rr + S::TPC * x;
+      if (i < NP) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          ws[cc * S::LDW + a * NP + i] = rG[3 * a] * r0[x] + rG[3 * a + 1] * r1[x] + rG[3 * a + 2] * r2[x];
+      }
+    }
+    __syncthreads();
+    if (t + gridDim.x < ntiles) load(t + gridDim.x);
+    if (mma) {
+      f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
+      auto bval = [&](int sp) __attribute__((always_inline)) {
+        const int i = 4 * (sp / 3) + g;
+        const double v = ws[n * S::LDW + (sp % 3) * NP + min(i, NP - 1)];
+        return i < NP ? v : 0.0;
+      };
+      double bcur = bval(0);
+#pragma unroll
+      for (int sp = 0; sp < S::KT; ++sp) {
+        const double bnxt = sp + 1 < S::KT ? bval(sp + 1) : 0.0;
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[sp], bcur, acc, 0, 0, 0);
+        bcur = bnxt;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = 16 * w + 4 * q + g;
+        if (j < NP) ostg[n * NP + j] = acc[q];
+      }
+    }
+    __syncthreads();
+    double* __restrict__ dst = gu + (int64_t)col0 * NP;
+    for (int x = tid; x < cnt; x += S::NTH) dst[x] = ostg[x];
+  }
+}
+
+// ------------------------------------------------------------------ pass B: gG
+
+template <int NP>
+struct AdjCrB {
+  static constexpr int NTH = WAVE * ADJCR_WPB;
+  static constexpr int KS = Shape<NP>::KS64;
+  static constexpr int LD = NP + 1;                    // odd row stride of the u stage
+  static constexpr int NLD = (16 * NP + NTH - 1) / NTH;
+  static_assert(Shape<NP>::NCHUNK <= ADJCR_WPB, "one wave per output chunk");
+};
+
+template <int NP>
+__global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double* __restrict__ D,
+                                                                  const double* __restrict__ u,
+                                                                  const double* __restrict__ gout,
+                                                                  double* __restrict__ gG, uint32_t K, uint32_t F,
+                                                                  int64_t plane, uint32_t E, uint32_t nsub,
+                                                                  uint32_t ntiles) {
+  using Sh = Shape<NP>;
+  using S = AdjCrB<NP>;
+  __shared__ double us[16 * S::LD];
+  __shared__ double red[ADJCR_WPB][16][9];  // per wave and column, summed over sub-tiles
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int n = lane & 15, g = lane >> 4;
+  const int w = tid >> 6;
+  const bool mma = w < Sh::NCHUNK;
+  const int ch = mma ? w : 0;
+  double areg[3][S::KS];
+#pragma unroll
+  for (int tt = 0; tt < 3; ++tt) {
+    const int T = 3 * ch + tt;
+#pragma unroll
+    for (int s = 0; s < S::KS; ++s) areg[tt][s] = (mma && T < Sh::MT) ? afrag_f64<NP>(D, T, s, lane) : 0.0;
+  }
+  // columns of tile t (whole elements) and of its sub-tile `sub`
+  auto tile_cols = [&](uint32_t tt) __attribute__((always_inline)) {
+    const uint32_t ne = min(E, K - tt * E);
+    return F <= 16 ? ne * F : F;
+  };
+  double ur[S::NLD];
+  auto load = [&](uint32_t tt, uint32_t sub) __attribute__((always_inline)) {
+    const uint32_t c0 = tt * E * F + 16 * sub;
+    const int cnt = (int)min(16u, tile_cols(tt) - 16 * sub) * NP;
+    const double* __restrict__ src = u + (int64_t)c0 * NP;
+#pragma unroll
+    for (int q = 0; q < S::NLD; ++q) {
+      const int x = tid + S::NTH * q;
+      ur[q] = x < cnt ? src[x] : 0.0;
+    }
+  };
+  uint32_t t = blockIdx.x, sub = 0;
+  if (t < ntiles) load(t, 0);
+  while (t < ntiles) {
+    const uint32_t ncolt = tile_cols(t);
+    const uint32_t c0 = t * E * F + 16 * sub;
+    const uint32_t nc = min(16u, ncolt - 16 * sub);  // valid columns of this sub-tile
+#pragma unroll
+    for (int q = 0; q < S::NLD; ++q) {
+      const int x = tid + S::NTH * q;
+      if (x < 16 * NP) us[(x / NP) * S::LD + (x % NP)] = ur[q];
+    }
+    __syncthreads();
+    const bool last = sub + 1 == nsub;
+    const uint32_t t_next = last ? t + gridDim.x : t;
+    const uint32_t sub_next = last ? 0u : sub + 1;
+    if (t_next < ntiles) load(t_next, sub_next);
+    if (mma) {
+      f64x4 acc[3];
+#pragma unroll
+      for (int tt = 0; tt < 3; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
+      auto bval = [&](int s) __attribute__((always_inline)) {
+        const int j = 4 * s + g;
+        const double v = us[n * S::LD + min(j, NP - 1)];
+        return j < NP ? v : 0.0;
+      };
+      double bcur = bval(0);
+#pragma unroll
+      for (int s = 0; s < S::KS; ++s) {
+        const double bnxt = s + 1 < S::KS ? bval(s + 1) : 0.0;
+#pragma unroll
+        for (int tt = 0; tt < 3; ++tt)
+          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[tt][s], bcur, acc[tt], 0, 0, 0);
+        bcur = bnxt;
+      }
+      // P[3a+b] = sum over this lane's nodes of gout_b * (D_a u)
+      const bool valid = (uint32_t)n < nc;
+      const int64_t cb = (int64_t)(c0 + (valid ? n : 0)) * NP;
+      double P[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) P[c] = 0.0;
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int tau = 4 * ch + x;
+        const int i = 4 * tau + g;
+        if (tau < Sh::TRIP && i < NP && valid) {
+          const double g0 = gout[cb + i], g1 = gout[plane + cb + i], g2 = gout[2 * plane + cb + i];
+#pragma unroll
+          for (int a = 0; a < 3; ++a) {
+            const int l = 3 * x + a;
+            const double R = acc[l >> 2][l & 3];
+            P[3 * a] += g0 * R;
+            P[3 * a + 1] += g1 * R;
+            P[3 * a + 2] += g2 * R;
+          }
+        }
+      }
+#pragma unroll
+      for (int c = 0; c < 9; ++c) {
+        P[c] += __shfl_xor(P[c], 16);
+        P[c] += __shfl_xor(P[c], 32);
+      }
+      if (g == 0) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) red[w][n][c] = (sub == 0 ? 0.0 : red[w][n][c]) + P[c];
+      }
+    }
+    __syncthreads();
+    if (last) {
+      // element e of the tile: its columns (all 16 lanes' sums when F > 16),
+      // each summed over the waves in order
+      const uint32_t ne = min(E, K - t * E);
+      if ((uint32_t)tid < ne * 9) {
+        const int e = tid / 9, c = tid % 9;
+        const int lo = F <= 16 ? e * (int)F : 0;
+        const int hi = F <= 16 ? lo + (int)F : 16;
+        double s = 0.0;
+        for (int m = lo; m < hi; ++m) {
+          double sw = 0.0;
+          for (int ww = 0; ww < Sh::NCHUNK; ++ww) sw += red[ww][m][c];
+          s += sw;
+        }
+        gG[(int64_t)(t * E + e) * 9 + c] = s;
+      }
+    }
+    t = t_next;
+    sub = sub_next;
+  }
+}
+
+}  // namespace dgvol

@@ -17,6 +17,7 @@
 
 #include "dgvol.h"
 #include "dgvol_adjoint.hpp"
+#include "dgvol_adjoint_cr.hpp"
 #include "dgvol_device.hpp"
 #include "dgvol_forward.hpp"
 #include "dgvol_global.hpp"
@@ -183,22 +184,39 @@ static dg_status launch_adj_f64(const double* D, const double* G, const double* 
   const uint32_t nsub = F <= 16 ? 1u : ceil_div((uint64_t)F, 16);
   const uint32_t ntiles = ceil_div((uint64_t)K, E);
   int err = DG_OK;
-  if (NP <= 56 && F <= 16) {
-    auto kern = adj_f64_staged_kernel<(NP <= 56 ? NP : 56), ADJ_WPB>;
-    const int cap = resident_blocks(kern, WAVE * ADJ_WPB, -1, &err);
+  if constexpr (NP >= 84) {
+    // two chunk-register passes: gu, then gG
+    const uint64_t ncols = (uint64_t)K * (uint64_t)F;
+    const uint32_t tiles_a = ceil_div(ncols, 16);
+    auto ka = adjcr_gu_kernel<NP>;
+    const int cap_a = resident_blocks(ka, WAVE * ADJCR_WPB, -1, &err);
     if (err != DG_OK) return err;
-    const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, ADJ_WPB), (uint32_t)cap);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * ADJ_WPB), 0, stream, D, G, u, gout, gu, gG, (uint32_t)K,
-                       (uint32_t)F, (int64_t)K * F * NP, E, ntiles);
+    hipLaunchKernelGGL(ka, dim3(std::min<uint32_t>(tiles_a, (uint32_t)cap_a)), dim3(WAVE * ADJCR_WPB), 0, stream, D, G,
+                       gout, gu, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP, tiles_a);
+    auto kb = adjcr_gG_kernel<NP>;
+    const int cap_b = resident_blocks(kb, WAVE * ADJCR_WPB, -1, &err);
+    if (err != DG_OK) return err;
+    hipLaunchKernelGGL(kb, dim3(std::min<uint32_t>(ntiles, (uint32_t)cap_b)), dim3(WAVE * ADJCR_WPB), 0, stream, D, u,
+                       gout, gG, (uint32_t)K, (uint32_t)F, (int64_t)ncols * NP, E, nsub, ntiles);
+    return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
   } else {
-    auto kern = adj_f64_kernel<NP, ADJ_WPB>;
-    const int cap = resident_blocks(kern, WAVE * ADJ_WPB, -1, &err);
-    if (err != DG_OK) return err;
-    const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, ADJ_WPB), (uint32_t)cap);
-    hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * ADJ_WPB), 0, stream, D, G, u, gout, gu, gG, (uint32_t)K,
-                       (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
+    if (F <= 16) {
+      auto kern = adj_f64_staged_kernel<NP, ADJ_WPB>;
+      const int cap = resident_blocks(kern, WAVE * ADJ_WPB, -1, &err);
+      if (err != DG_OK) return err;
+      const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, ADJ_WPB), (uint32_t)cap);
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * ADJ_WPB), 0, stream, D, G, u, gout, gu, gG, (uint32_t)K,
+                         (uint32_t)F, (int64_t)K * F * NP, E, ntiles);
+    } else {
+      auto kern = adj_f64_kernel<NP, ADJ_WPB>;
+      const int cap = resident_blocks(kern, WAVE * ADJ_WPB, -1, &err);
+      if (err != DG_OK) return err;
+      const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, ADJ_WPB), (uint32_t)cap);
+      hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * ADJ_WPB), 0, stream, D, G, u, gout, gu, gG, (uint32_t)K,
+                         (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
+    }
+    return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
   }
-  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
 
 // Partial sums of the D cotangent: a pure function of the problem size, so
