@@ -162,6 +162,20 @@ def test_adjoint_small(K, F):
         _check_adjoint(D, G, u, gout, host(gu), host(gG))
 
 
+@pytest.mark.parametrize("N,K,F", [(5, 3000, 3), (5, 700, 20), (6, 900, 3), (7, 600, 3), (7, 300, 20)])
+def test_adjoint_deterministic(N, K, F):
+    """Every adjoint path (staged, general, two-pass) gives the same bits on
+    every run: gG is summed in a fixed order, with no atomics."""
+    _say(f"adjoint determinism N={N} K={K} F={F}")
+    D, G, u = make_case(N, K, F, 650 + N + F)
+    gout = np.random.default_rng(651 + N).standard_normal((3, K, F, oracle.num_nodes(N)))
+    Dd, Gd, ud, gd = dev(D), dev(G), dev(u), dev(gout)
+    gu1, gG1 = (host(x) for x in dgvol.dg_volume_adjoint(Dd, Gd, ud, gd))
+    gu2, gG2 = (host(x) for x in dgvol.dg_volume_adjoint(Dd, Gd, ud, gd))
+    assert np.array_equal(gu1, gu2) and np.array_equal(gG1, gG2)
+    _check_adjoint(D, G, u, gout, gu1, gG1)
+
+
 def test_adjoint_workload5_full_size_sampled():
     """Order 5, K=2^19, F=3, loss = sum(out^2) so gout = 2 out; 2048 sampled elements."""
     N, K, F = 5, 1 << 19, 3
