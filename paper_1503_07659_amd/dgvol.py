@@ -1,14 +1,16 @@
 """Python binding of libdgvol.so (argument marshalling only).
 
 The functions named like the C entry points (``dg_volume``,
-``dg_volume_adjoint``, ``dg_volume_f32s``) take torch tensors on the GPU,
-check dtype/device/shape/contiguity, and pass raw device pointers plus torch's
-current HIP stream to the library.  Every arithmetic step runs in the HIP
-kernels; there is no CPU or PyTorch fallback: if the library is missing or
+``dg_volume_adjoint``, ``dg_volume_grad_d``, ``dg_volume_f32s``,
+``dg_volume_batched`` and the two calibration calls) take torch tensors on the
+GPU, check dtype/device/shape/contiguity, and pass raw device pointers plus
+torch's current HIP stream to the library.  Every arithmetic step runs in the
+HIP kernels; there is no CPU or PyTorch fallback: if the library is missing or
 fails to load, every call raises.
 
-``DGVolume`` is a ``torch.autograd.Function`` whose backward calls the adjoint
-kernel (gradients with respect to u and G; D is treated as a constant).
+``DGVolume`` is a ``torch.autograd.Function``: its backward calls the adjoint
+kernels for the gradients with respect to u and G, and ``dg_volume_grad_d``
+for the gradient with respect to D when D requires one.
 """
 
 import ctypes
@@ -121,7 +123,7 @@ def _check_tensor(name, t, dtype, shape, device=None):
         raise ValueError(f"{name} must be contiguous")
 
 
-def _sizes(u, D):
+def _sizes(u):
     if u.dim() != 3:
         raise ValueError(f"u must be (K, F, Np), got shape {tuple(u.shape)}")
     K, F, Np = u.shape
@@ -132,7 +134,7 @@ def _sizes(u, D):
 
 def dg_volume(D, G, u, out=None):
     """FP64 forward: out[b,k,f,i] = sum_a G[k,3a+b] (D_a u[k,f])[i]; returns out (3, K, F, Np)."""
-    K, F, Np = _sizes(u, D)
+    K, F, Np = _sizes(u)
     dev = u.device
     _check_tensor("u", u, torch.float64, (K, F, Np))
     _check_tensor("D", D, torch.float64, (3, Np, Np), dev)
@@ -149,7 +151,7 @@ def dg_volume(D, G, u, out=None):
 
 def dg_volume_adjoint(D, G, u, gout, gu=None, gG=None):
     """FP64 adjoint w.r.t. u and G for the cotangent gout (3, K, F, Np); returns (gu, gG)."""
-    K, F, Np = _sizes(u, D)
+    K, F, Np = _sizes(u)
     dev = u.device
     _check_tensor("u", u, torch.float64, (K, F, Np))
     _check_tensor("D", D, torch.float64, (3, Np, Np), dev)
@@ -182,7 +184,7 @@ def dg_volume_grad_d(G, u, gout, gD=None, work=None):
     ``work`` is optional device scratch (uint8, at least ``grad_d_workspace_bytes``);
     one is allocated when it is not given."""
     _check_tensor("u", u, torch.float64, tuple(u.shape))
-    K, F, Np = _sizes(u, None)
+    K, F, Np = _sizes(u)
     dev = u.device
     _check_tensor("G", G, torch.float64, (K, 9), dev)
     _check_tensor("gout", gout, torch.float64, (3, K, F, Np), dev)
@@ -204,7 +206,7 @@ def dg_volume_grad_d(G, u, gout, gD=None, work=None):
 
 def dg_volume_f32s(D, G, u, out=None):
     """FP32 storage, split-BF16 products: same contract as dg_volume with float32 tensors."""
-    K, F, Np = _sizes(u, D)
+    K, F, Np = _sizes(u)
     dev = u.device
     _check_tensor("u", u, torch.float32, (K, F, Np))
     _check_tensor("D", D, torch.float32, (3, Np, Np), dev)
@@ -238,7 +240,7 @@ def dg_volume_batched(groups, form=FORM_F64, outs=None, bodies=None, costs=None)
     arr = (DgGroup * max(1, len(groups)))()
     res = []
     for gi, (D, G, u) in enumerate(groups):
-        K, Fg, Np = _sizes(u, D)
+        K, Fg, Np = _sizes(u)
         if Fg != F:
             raise ValueError("all groups of a batch share F")
         _check_tensor("u", u, dtype, (K, F, Np), dev)
