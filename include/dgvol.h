@@ -32,7 +32,8 @@
  *     any input or each other.
  *   - Arguments are validated before any HIP call; on error nothing is
  *     launched and no output is touched.
- *   - K == 0 is a no-op that returns DG_OK (pointers may then be NULL).
+ *   - K == 0 is a no-op that returns DG_OK (pointers may then be NULL),
+ *     except for dg_volume_grad_d, whose output gD is then set to zero.
  *   - Pointers must be aligned to their element size (8 bytes for double,
  *     4 bytes for float).
  *   - Supported node counts: Np in {4, 10, 20, 35, 56, 84, 120} (N = 1..7).
