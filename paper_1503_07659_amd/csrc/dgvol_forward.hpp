@@ -747,33 +747,38 @@ __device__ __forceinline__ void fwd_f32s_staged_multi(const FwdArgs<float>& p, u
     f32x4 acc[TPI][Sh::MT];
 #pragma unroll
     for (int r = 0; r < TPI; ++r) {
-      Bf16x8Bits bh[Sh::KS16], bl[Sh::KS16];
 #pragma unroll
-      for (int s = 0; s < Sh::KS16; ++s) {
+      for (int T = 0; T < Sh::MT; ++T) acc[r][T] = f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+    // one k-step at a time: the B halves of every tile, then each A fragment
+    // read once for all TPI tiles
+#pragma unroll
+    for (int s = 0; s < Sh::KS16; ++s) {
+      Bf16x8Bits bh[TPI], bl[TPI];
+#pragma unroll
+      for (int r = 0; r < TPI; ++r) {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int j = 32 * s + 8 * g + e;
-          split_bf16(j < NP ? su[r * TILE + n * NP + j] : 0.0f, bh[s].v[e], bl[s].v[e]);
+          split_bf16(j < NP ? su[r * TILE + n * NP + j] : 0.0f, bh[r].v[e], bl[r].v[e]);
         }
       }
 #pragma unroll
-      for (int T = 0; T < Sh::MT; ++T) acc[r][T] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int s = 0; s < Sh::KS16; ++s) {
-#pragma unroll
-        for (int T = 0; T < Sh::MT; ++T) {
-          Bf16x8Bits ah, al;
-          if constexpr (ALDS) {
-            ah = ahi[(T * Sh::KS16 + s) * WAVE + lane];
-            al = alo[(T * Sh::KS16 + s) * WAVE + lane];
-          } else {
-            afrag_bf16<NP>(p.D, T, s, lane, ah, al);
-          }
-          acc[r][T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al), as_bf16x8(bh[s]), acc[r][T], 0, 0, 0);
-          acc[r][T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bl[s]), acc[r][T], 0, 0, 0);
-          acc[r][T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bh[s]), acc[r][T], 0, 0, 0);
-          __builtin_amdgcn_sched_barrier(0);
+      for (int T = 0; T < Sh::MT; ++T) {
+        Bf16x8Bits ah, al;
+        if constexpr (ALDS) {
+          ah = ahi[(T * Sh::KS16 + s) * WAVE + lane];
+          al = alo[(T * Sh::KS16 + s) * WAVE + lane];
+        } else {
+          afrag_bf16<NP>(p.D, T, s, lane, ah, al);
         }
+#pragma unroll
+        for (int r = 0; r < TPI; ++r) {
+          acc[r][T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al), as_bf16x8(bh[r]), acc[r][T], 0, 0, 0);
+          acc[r][T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bl[r]), acc[r][T], 0, 0, 0);
+          acc[r][T] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(ah), as_bf16x8(bh[r]), acc[r][T], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
     wave_sync();
