@@ -13,6 +13,7 @@
 #include "dgvol.h"
 #include "dgvol_device.hpp"
 #include "dgvol_forward.hpp"
+#include "dgvol_forward_f32s.hpp"
 #include "dgvol_layout.hpp"
 
 namespace dgvol {

@@ -4,7 +4,8 @@
 // Adjoint:  gu = sum_a D_a^T W_a with W_a = sum_b G[3a+b] gout_b;
 //           gG[3a+b] = sum_{f,i} gout_b[i] (D_a u)[i].
 // Definitions, layouts and error behaviour are documented in include/dgvol.h;
-// the forward data-movement schemes in dgvol_forward.hpp, the adjoint in
+// the forward data-movement schemes in dgvol_forward.hpp (FP64) and
+// dgvol_forward_f32s.hpp (split-BF16), the adjoint in
 // dgvol_adjoint.hpp, the D cotangent in dgvol_gradd.hpp, the register layout
 // of the products in dgvol_layout.hpp, the entry kernels in dgvol_global.hpp.
 // This file holds the host side: launch configuration, validation, the ABI.
@@ -20,6 +21,7 @@
 #include "dgvol_adjoint_cr.hpp"
 #include "dgvol_device.hpp"
 #include "dgvol_forward.hpp"
+#include "dgvol_forward_f32s.hpp"
 #include "dgvol_global.hpp"
 #include "dgvol_gradd.hpp"
 #include "dgvol_layout.hpp"
