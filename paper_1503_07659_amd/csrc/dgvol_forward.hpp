@@ -313,8 +313,18 @@ __device__ __forceinline__ void fwd_f64_staged_body(const FwdArgs<double>& p, ui
 
 // ------------------------------------------------------------------ FP64 chunk-register
 
-template <int NP>
-constexpr int chunk_ld() { return NP + 1; }  // odd row stride: B-operand reads spread over banks
+// Row stride of the staged u rows.  FP64: odd, so the 8-byte B-operand reads
+// of a wave spread over the banks.  FP32: the smallest stride >= Np that is 4
+// modulo 8 words, so each lane's 8 consecutive operand words are two aligned
+// 16-byte reads and the 16 lanes of a read group start on distinct banks.
+template <int NP, int WORD>
+constexpr int chunk_ld() { return WORD == 8 ? NP + 1 : ((NP + 3) / 8) * 8 + 4; }
+
+// Row stride of the output tile: each wave writes word (column n, node 4 tau + g)
+// from all 64 lanes.  FP64: Np + 2 (Np = 0 mod 4), so the two half-wave groups of
+// an 8-byte write hit distinct banks; FP32: a multiple of 4 that is 4 mod 8.
+template <int NP, int WORD>
+constexpr int chunk_old() { return WORD == 8 ? NP + 2 : ((NP + 3) / 8) * 8 + 4; }
 
 // Column tiles the workgroup shares per iteration of the chunk-register bodies:
 // more tiles per iteration means fewer barriers per byte and more bytes in flight,
@@ -325,7 +335,9 @@ constexpr int chunk_tpw() { return WORD == 4 ? 4 : (NP >= 120 ? 1 : 2); }
 template <int NP, int WORD>
 constexpr int chunk_lds() {
   constexpr int TPW = chunk_tpw<NP, WORD>();
-  return align16(TPW * 16 * chunk_ld<NP>() * WORD) + align16(3 * TPW * 16 * NP * WORD) + TPW * 16 * 9 * WORD;
+  // (+32 bytes: the FP32 operand reads of the last row may run past it by up to 7 words)
+  return align16(TPW * 16 * chunk_ld<NP, WORD>() * WORD + 32) + align16(3 * TPW * 16 * chunk_old<NP, WORD>() * WORD) +
+         TPW * 16 * 9 * WORD;
 }
 
 template <int NP, int WPB>
@@ -342,15 +354,17 @@ __device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid,
                                               ChunkFn&& chunk) {
   constexpr int WORD = sizeof(T);
   constexpr int TPW = chunk_tpw<NP, WORD>();
-  constexpr int LD = chunk_ld<NP>();
+  constexpr int LD = chunk_ld<NP, WORD>();
   constexpr int SUP = TPW * 16 * NP;        // words of one plane of the super-tile
+  constexpr int OLD = chunk_old<NP, WORD>();
+  constexpr int OSUP = TPW * 16 * OLD;      // words of one plane of the output tile
   constexpr int NT = WAVE * WPB;
   constexpr int NLD = (SUP + NT - 1) / NT;  // u words loaded per thread per iteration
   constexpr int GMAX = TPW * 16 * 9;        // geometric-factor words of at most TPW*16 elements
   constexpr int NG = (GMAX + NT - 1) / NT;  // G words loaded per thread per iteration
   T* us = reinterpret_cast<T*>(lds);
-  T* ostg = reinterpret_cast<T*>(lds + align16(TPW * 16 * LD * WORD));
-  T* gs = reinterpret_cast<T*>(lds + align16(TPW * 16 * LD * WORD) + align16(3 * SUP * WORD));
+  T* ostg = reinterpret_cast<T*>(lds + align16(TPW * 16 * LD * WORD + 32));
+  T* gs = reinterpret_cast<T*>(lds + align16(TPW * 16 * LD * WORD + 32) + align16(3 * OSUP * WORD));
   const int tid = threadIdx.x;
   const uint32_t nsup = (p.ntiles + TPW - 1) / TPW;
   T ur[NLD];
@@ -399,7 +413,7 @@ __device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid,
 #pragma unroll
       for (int q = 0; q < NLD; ++q) {
         const int x = tid + NT * q;
-        if (x < cnt) ob[x] = ostg[bb * SUP + x];
+        if (x < cnt) ob[x] = ostg[bb * OSUP + (x / NP) * OLD + (x % NP)];
       }
     }
   }
@@ -411,9 +425,10 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
   using Sh = Shape<NP>;
   static_assert(WPB >= Sh::NCHUNK, "one wave per output chunk");
   constexpr int KS = Sh::KS64;
-  constexpr int LD = chunk_ld<NP>();
+  constexpr int LD = chunk_ld<NP, 8>();
   constexpr int TPW = chunk_tpw<NP, 8>();
-  constexpr int SUP = TPW * 16 * NP;
+  constexpr int OLD = chunk_old<NP, 8>();
+  constexpr int OSUP = TPW * 16 * OLD;
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
   const int w = threadIdx.x >> 6;
@@ -459,7 +474,7 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
           const int l0 = 3 * x;
 #pragma unroll
           for (int bb = 0; bb < 3; ++bb)
-            ostg[bb * SUP + cl * NP + i] = gs[e * 9 + bb] * acc[l0 >> 2][l0 & 3] +
+            ostg[bb * OSUP + cl * OLD + i] = gs[e * 9 + bb] * acc[l0 >> 2][l0 & 3] +
                                            gs[e * 9 + 3 + bb] * acc[(l0 + 1) >> 2][(l0 + 1) & 3] +
                                            gs[e * 9 + 6 + bb] * acc[(l0 + 2) >> 2][(l0 + 2) & 3];
         }

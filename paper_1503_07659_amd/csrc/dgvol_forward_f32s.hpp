@@ -381,9 +381,10 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
   using Sh = Shape<NP>;
   static_assert(WPB >= Sh::NCHUNK, "one wave per output chunk");
   constexpr int KS = Sh::KS16;
-  constexpr int LD = chunk_ld<NP>();
+  constexpr int LD = chunk_ld<NP, 4>();
   constexpr int TPW = chunk_tpw<NP, 4>();
-  constexpr int SUP = TPW * 16 * NP;
+  constexpr int OLD = chunk_old<NP, 4>();
+  constexpr int OSUP = TPW * 16 * OLD;
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
   const int w = threadIdx.x >> 6;
@@ -414,10 +415,12 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
         Bf16x8Bits bh, bl;
+        const f32x4* bp = reinterpret_cast<const f32x4*>(us + cl * LD + 32 * s + 8 * g);
+        const f32x4 v0 = bp[0], v1 = bp[1];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
           const int j = 32 * s + 8 * g + e;
-          const float v = us[cl * LD + min(j, NP - 1)];
+          const float v = e < 4 ? v0[e] : v1[e - 4];
           split_bf16(j < NP ? v : 0.0f, bh.v[e], bl.v[e]);
         }
 #pragma unroll
@@ -437,7 +440,7 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
           const int l0 = 3 * x;
 #pragma unroll
           for (int bb = 0; bb < 3; ++bb)
-            ostg[bb * SUP + cl * NP + i] = gs[e * 9 + bb] * acc[l0 >> 2][l0 & 3] +
+            ostg[bb * OSUP + cl * OLD + i] = gs[e * 9 + bb] * acc[l0 >> 2][l0 & 3] +
                                            gs[e * 9 + 3 + bb] * acc[(l0 + 1) >> 2][(l0 + 1) & 3] +
                                            gs[e * 9 + 6 + bb] * acc[(l0 + 2) >> 2][(l0 + 2) & 3];
         }
