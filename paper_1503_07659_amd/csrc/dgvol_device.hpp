@@ -55,25 +55,26 @@ __device__ __forceinline__ int tswz(int lane, int s) { return lane ^ ((s & 3) <<
 
 // ------------------------------------------------------------------ BF16 split
 
-// Round FP32 to the nearest BF16 (ties to even) in integer arithmetic; returns
-// the FP32 bit pattern with the low 16 bits clear.  NaN stays a quiet NaN.
-__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
-  const uint32_t b = __float_as_uint(x);
-  if ((b & 0x7f800000u) == 0x7f800000u && (b & 0x007fffffu) != 0u) return (b | 0x00400000u) & 0xffff0000u;
-  return (b + 0x7fffu + ((b >> 16) & 1u)) & 0xffff0000u;
-}
-
-// x = hi + lo + O(2^-18 |x|): hi = bf16(x), lo = bf16(x - hi), as BF16 bit patterns.
-__device__ __forceinline__ void split_bf16(float x, uint16_t& hi, uint16_t& lo) {
-  const uint32_t h = bf16_rne_bits(x);
-  const float r = x - __uint_as_float(h);  // exact in FP32
-  hi = (uint16_t)(h >> 16);
-  lo = (uint16_t)(bf16_rne_bits(r) >> 16);
-}
-
 struct alignas(16) Bf16x8Bits {
   uint16_t v[8];
 };
+
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+
+// x = hi + lo + O(2^-18 |x|) with hi = bf16(x), lo = bf16(x - hi), for two
+// values at once on the packed FP32 -> BF16 converter (round to nearest even;
+// NaN stays NaN): elements e, e+1 of hi and lo as BF16 bit patterns.
+__device__ __forceinline__ void split_bf16_pair(float x0, float x1, Bf16x8Bits& hi, Bf16x8Bits& lo, int e) {
+  const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2v{x0, x1}, bf16x2));
+  const float r0 = x0 - __uint_as_float(h << 16);          // exact in FP32
+  const float r1 = x1 - __uint_as_float(h & 0xffff0000u);
+  const uint32_t l = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2v{r0, r1}, bf16x2));
+  hi.v[e] = (uint16_t)(h & 0xffffu);
+  hi.v[e + 1] = (uint16_t)(h >> 16);
+  lo.v[e] = (uint16_t)(l & 0xffffu);
+  lo.v[e + 1] = (uint16_t)(l >> 16);
+}
 
 __device__ __forceinline__ bf16x8 as_bf16x8(const Bf16x8Bits& x) { return __builtin_bit_cast(bf16x8, x); }
 
@@ -89,10 +90,11 @@ __device__ __forceinline__ void afrag_bf16(const float* __restrict__ D, int T, i
   const int a = slot_dir(sigma), i = slot_node(sigma, g);
   const bool row_ok = sigma < Shape<NP>::SLOTS && i < NP;
 #pragma unroll
-  for (int e = 0; e < 8; ++e) {
+  for (int e = 0; e < 8; e += 2) {
     const int j = 32 * s + 8 * kk + e;
-    const float x = (row_ok && j < NP) ? D[(a * NP + i) * NP + j] : 0.0f;
-    split_bf16(x, hi.v[e], lo.v[e]);
+    const float x0 = (row_ok && j < NP) ? D[(a * NP + i) * NP + j] : 0.0f;
+    const float x1 = (row_ok && j + 1 < NP) ? D[(a * NP + i) * NP + j + 1] : 0.0f;
+    split_bf16_pair(x0, x1, hi, lo, e);
   }
 }
 

@@ -118,9 +118,9 @@ __device__ __forceinline__ void fwd_f32s_staged_single(const FwdArgs<float>& p, 
 #pragma unroll
     for (int s = 0; s < Sh::KS16; ++s) {
 #pragma unroll
-      for (int e = 0; e < 8; ++e) {
+      for (int e = 0; e < 8; e += 2) {
         const int j = 32 * s + 8 * g + e;
-        split_bf16(j < NP ? stg[n * NP + j] : 0.0f, bh[s].v[e], bl[s].v[e]);
+        split_bf16_pair(j < NP ? stg[n * NP + j] : 0.0f, j + 1 < NP ? stg[n * NP + j + 1] : 0.0f, bh[s], bl[s], e);
       }
     }
     const uint32_t col = col0 + n;
@@ -299,9 +299,10 @@ __device__ __forceinline__ void fwd_f32s_staged_multi(const FwdArgs<float>& p, u
 #pragma unroll
       for (int r = 0; r < TPI; ++r) {
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < 8; e += 2) {
           const int j = 32 * s + 8 * g + e;
-          split_bf16(j < NP ? su[r * TILE + n * NP + j] : 0.0f, bh[r].v[e], bl[r].v[e]);
+          split_bf16_pair(j < NP ? su[r * TILE + n * NP + j] : 0.0f, j + 1 < NP ? su[r * TILE + n * NP + j + 1] : 0.0f,
+                          bh[r], bl[r], e);
         }
       }
 #pragma unroll
@@ -418,10 +419,10 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
         const f32x4* bp = reinterpret_cast<const f32x4*>(us + cl * LD + 32 * s + 8 * g);
         const f32x4 v0 = bp[0], v1 = bp[1];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
+        for (int e = 0; e < 8; e += 2) {
           const int j = 32 * s + 8 * g + e;
-          const float v = e < 4 ? v0[e] : v1[e - 4];
-          split_bf16(j < NP ? v : 0.0f, bh.v[e], bl.v[e]);
+          const float x0 = e < 4 ? v0[e] : v1[e - 4], x1 = e < 4 ? v0[e + 1] : v1[e - 3];
+          split_bf16_pair(j < NP ? x0 : 0.0f, j + 1 < NP ? x1 : 0.0f, bh, bl, e);
         }
 #pragma unroll
         for (int tt = 0; tt < 3; ++tt) {
