@@ -53,6 +53,12 @@ constexpr int fwd_table_doubles() { return Shape<NP>::MT * Shape<NP>::KS64 * WAV
 // XOR swizzle of the A table: entry `lane` of row (T, s) sits at lane ^ ((s & 3) << 2).
 __device__ __forceinline__ int tswz(int lane, int s) { return lane ^ ((s & 3) << 2); }
 
+// Output planes are written once and not read again by the launch; streaming
+// (non-temporal) stores measured faster for them on MI355X than ordinary ones
+// (1:3 read:write stream +2 %, split-BF16 forward 10-16 %).
+template <class T>
+__device__ __forceinline__ void store_stream(T* p, const T& v) { __builtin_nontemporal_store(v, p); }
+
 // ------------------------------------------------------------------ BF16 split
 
 struct alignas(16) Bf16x8Bits {
@@ -60,16 +66,16 @@ struct alignas(16) Bf16x8Bits {
 };
 
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
-typedef float f32x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 // x = hi + lo + O(2^-18 |x|) with hi = bf16(x), lo = bf16(x - hi), for two
 // values at once on the packed FP32 -> BF16 converter (round to nearest even;
 // NaN stays NaN): elements e, e+1 of hi and lo as BF16 bit patterns.
 __device__ __forceinline__ void split_bf16_pair(float x0, float x1, Bf16x8Bits& hi, Bf16x8Bits& lo, int e) {
-  const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2v{x0, x1}, bf16x2));
+  const uint32_t h = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{x0, x1}, bf16x2));
   const float r0 = x0 - __uint_as_float(h << 16);          // exact in FP32
   const float r1 = x1 - __uint_as_float(h & 0xffff0000u);
-  const uint32_t l = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2v{r0, r1}, bf16x2));
+  const uint32_t l = __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2{r0, r1}, bf16x2));
   hi.v[e] = (uint16_t)(h & 0xffffu);
   hi.v[e + 1] = (uint16_t)(h >> 16);
   lo.v[e] = (uint16_t)(l & 0xffffu);

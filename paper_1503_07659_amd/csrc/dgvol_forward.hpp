@@ -157,7 +157,7 @@ __device__ __forceinline__ void fwd_f64_staged_single(const FwdArgs<double>& p, 
 #pragma unroll
       for (int q = 0; q < NRAW; ++q) {
         const int x = lane + WAVE * q;
-        if (x < cnt) ob[x] = stg[x];
+        if (x < cnt) store_stream(&ob[x], stg[x]);
       }
       wave_sync();
     }
@@ -294,7 +294,7 @@ __device__ __forceinline__ void fwd_f64_staged_multi(const FwdArgs<double>& p, u
 #pragma unroll
       for (int q = 0; q < NRAW; ++q) {
         const int x = lane + WAVE * q;
-        if (x < cnt) ob[x] = su[x];
+        if (x < cnt) store_stream(&ob[x], su[x]);
       }
       wave_sync();
     }
@@ -413,7 +413,7 @@ __device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid,
 #pragma unroll
       for (int q = 0; q < NLD; ++q) {
         const int x = tid + NT * q;
-        if (x < cnt) ob[x] = ostg[bb * OSUP + (x / NP) * OLD + (x % NP)];
+        if (x < cnt) store_stream(&ob[x], ostg[bb * OSUP + (x / NP) * OLD + (x % NP)]);
       }
     }
   }

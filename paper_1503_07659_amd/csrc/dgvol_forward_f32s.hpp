@@ -34,8 +34,6 @@ constexpr int fwd_f32s_staged_lds() {
   return (bf16_table_fits<NP>() ? 2 * bf16_table_entries<NP>() * 16 : 0) + WPB * f32s_wave_floats<NP>() * 4;
 }
 
-typedef float f32x2 __attribute__((ext_vector_type(2)));
-
 // u, out and every plane start 8-byte aligned: the staged split-BF16 body then
 // moves pairs of floats (512-byte runs per instruction, as the FP64 body does).
 __host__ __device__ inline bool f32_pairs_ok(const FwdArgs<float>& p) {
@@ -166,13 +164,13 @@ __device__ __forceinline__ void fwd_f32s_staged_single(const FwdArgs<float>& p, 
 #pragma unroll
         for (int q = 0; q < NPAIR; ++q) {
           const int x = lane + WAVE * q;
-          if (x < TILE / 2) reinterpret_cast<f32x2*>(ob)[x] = reinterpret_cast<const f32x2*>(stg)[x];
+          if (x < TILE / 2) store_stream(&reinterpret_cast<f32x2*>(ob)[x], reinterpret_cast<const f32x2*>(stg)[x]);
         }
       } else {
 #pragma unroll
         for (int q = 0; q < NRAW; ++q) {
           const int x = lane + WAVE * q;
-          if (x < cnt) ob[x] = stg[x];
+          if (x < cnt) store_stream(&ob[x], stg[x]);
         }
       }
       wave_sync();
@@ -347,13 +345,13 @@ __device__ __forceinline__ void fwd_f32s_staged_multi(const FwdArgs<float>& p, u
 #pragma unroll
         for (int q = 0; q < NPAIR; ++q) {
           const int x = lane + WAVE * q;
-          if (x < RUN / 2) reinterpret_cast<f32x2*>(ob)[x] = reinterpret_cast<const f32x2*>(su)[x];
+          if (x < RUN / 2) store_stream(&reinterpret_cast<f32x2*>(ob)[x], reinterpret_cast<const f32x2*>(su)[x]);
         }
       } else {
 #pragma unroll
         for (int q = 0; q < NRAW; ++q) {
           const int x = lane + WAVE * q;
-          if (x < cnt) ob[x] = su[x];
+          if (x < cnt) store_stream(&ob[x], su[x]);
         }
       }
       wave_sync();

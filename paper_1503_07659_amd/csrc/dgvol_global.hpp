@@ -154,7 +154,8 @@ __global__ __launch_bounds__(WAVE* FWD_WPB) void batched_f32s_kernel(BatchArgs a
 // ------------------------------------------------------------------ stream calibration
 //
 // Reads n doubles once and writes `copies` scaled copies of them (dst[c*n + i]
-// = (c + 1) * src[i]) with contiguous 8-byte accesses.  With copies = 1 this is
+// = (c + 1) * src[i]) with contiguous 8-byte accesses, stored as the forward
+// kernels store their output planes (streaming stores).  With copies = 1 this is
 // a plain copy of known size (the scale of the hardware byte counters); with
 // copies = 3 it moves bytes in the forward kernel's 1 : 3 read : write mix with
 // no other work (the practical streaming ceiling for that mix).
@@ -163,7 +164,7 @@ __global__ __launch_bounds__(256) void stream_kernel(const double* __restrict__ 
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     const double v = src[i];
-    for (int32_t c = 0; c < copies; ++c) dst[c * n + i] = (double)(c + 1) * v;
+    for (int32_t c = 0; c < copies; ++c) store_stream(&dst[c * n + i], (double)(c + 1) * v);
   }
 }
 
