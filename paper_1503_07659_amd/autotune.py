@@ -93,11 +93,15 @@ def _time_body(form, body, D, G, u, out, reps):
     return float(np.median([ev[i].elapsed_time(ev[i + 1]) for i in range(reps)])) * 1e-3
 
 
-def tune(form, Np, F, target_bytes=256 << 20, reps=10, device=None, cache=None, save=True):
-    """Measure every available body for (form, Np, F); store and return the cache entry."""
+def tune(form, Np, F, target_bytes=256 << 20, min_tiles=1 << 15, reps=10, device=None, cache=None, save=True):
+    """Measure every available body for (form, Np, F); store and return the cache entry.
+
+    The problem moves at least ``target_bytes`` and holds at least ``min_tiles``
+    16-column tiles, so that at the high orders (few bytes per unit of matrix
+    work) the launch's ramp and tail do not inflate the time of a tile."""
     device = device or torch.device("cuda", torch.cuda.current_device())
     word = 8 if form == dgvol.FORM_F64 else 4
-    K = max(1024, int(target_bytes // (word * (4 * F * Np + 9))))
+    K = max(1024, int(target_bytes // (word * (4 * F * Np + 9))), -(-16 * min_tiles // F))
     D, G, u = _synthetic(form, Np, F, K, device)
     out = torch.empty((3, K, F, Np), dtype=u.dtype, device=device)
     ntiles = -(-K * F // 16)

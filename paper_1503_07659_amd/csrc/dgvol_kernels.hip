@@ -260,13 +260,13 @@ static double tile_cost_estimate(int form, int Np, uint32_t F) {
   const double peak = form == DG_FORM_F64 ? 78.6e12 : 2.5e15 / 3.0;  // three BF16 passes
   double eff;
   switch (Np) {
-    case 4: eff = form == DG_FORM_F64 ? 0.64 : 0.31; break;
-    case 10: eff = form == DG_FORM_F64 ? 0.61 : 0.38; break;
-    case 20: eff = form == DG_FORM_F64 ? 0.59 : 0.53; break;
-    case 35: eff = form == DG_FORM_F64 ? 0.60 : 0.55; break;
-    case 56: eff = form == DG_FORM_F64 ? 0.45 : 0.55; break;
-    case 84: eff = form == DG_FORM_F64 ? 0.38 : 0.49; break;
-    default: eff = form == DG_FORM_F64 ? 0.53 : 0.20; break;  // Np = 120
+    case 4: eff = form == DG_FORM_F64 ? 0.70 : 0.52; break;
+    case 10: eff = form == DG_FORM_F64 ? 0.70 : 0.68; break;
+    case 20: eff = form == DG_FORM_F64 ? 0.73 : 0.68; break;
+    case 35: eff = form == DG_FORM_F64 ? 0.58 : 0.68; break;
+    case 56: eff = form == DG_FORM_F64 ? 0.42 : 0.78; break;
+    case 84: eff = form == DG_FORM_F64 ? 0.40 : 0.68; break;
+    default: eff = form == DG_FORM_F64 ? 0.55 : 0.42; break;  // Np = 120
   }
   return std::max(bytes / bw, flops / peak) / eff;
 }
@@ -451,13 +451,31 @@ dg_status dg_volume_batched(const dg_group* groups, int32_t ngroups, int32_t F, 
   const int cap = form == DG_FORM_F64 ? resident_blocks(batched_f64_kernel, WAVE * FWD_WPB, lds, &err)
                                       : resident_blocks(batched_f32s_kernel, WAVE * FWD_WPB, lds, &err);
   if (err != DG_OK) return err;
-  // split the resident workgroups in proportion to cost; every group gets at least one
+  // Split the resident workgroups so that the largest cost per workgroup is as
+  // small as possible (Jefferson / D'Hondt apportionment): every group gets the
+  // whole part of its proportional share, at least one and at most what it can
+  // use, then each workgroup left goes to the group with the largest cost per
+  // workgroup.  Plain rounding of the shares can leave a small group one
+  // workgroup short, and that group then finishes last.
+  uint32_t nb[DG_MAX_GROUPS];
+  uint32_t used = 0;
+  for (int i = 0; i < ng; ++i) {
+    const uint32_t share = (uint32_t)((double)cap * cost[i] / total_cost);
+    nb[i] = std::max<uint32_t>(1u, std::min(share, max_blocks[i]));
+    used += nb[i];
+  }
+  while (used < (uint32_t)cap) {
+    int pick = -1;
+    for (int i = 0; i < ng; ++i)
+      if (nb[i] < max_blocks[i] && (pick < 0 || cost[i] * nb[pick] > cost[pick] * nb[i])) pick = i;
+    if (pick < 0) break;
+    ++nb[pick];
+    ++used;
+  }
   uint32_t begin = 0;
   for (int i = 0; i < ng; ++i) {
     a.wg_begin[i] = begin;
-    uint32_t nb = (uint32_t)std::llround((double)cap * cost[i] / total_cost);
-    nb = std::max<uint32_t>(1u, std::min(nb, max_blocks[i]));
-    begin += nb;
+    begin += nb[i];
   }
   for (int i = ng; i <= MAX_GROUPS; ++i) a.wg_begin[i] = begin;
   if (form == DG_FORM_F64)

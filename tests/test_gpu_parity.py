@@ -520,7 +520,7 @@ def test_autotuner_cache_and_tuned_launch(tmp_path, monkeypatch):
     monkeypatch.setenv("DGVOL_AUTOTUNE_CACHE", str(tmp_path / "cache.json"))
     _say("autotune")
     (tmp_path / "cache.json").write_text("{not json")  # a corrupt cache is ignored and rewritten
-    e = autotune.tune(dgvol.FORM_F64, 35, 3, target_bytes=32 << 20, reps=3)
+    e = autotune.tune(dgvol.FORM_F64, 35, 3, target_bytes=32 << 20, min_tiles=1 << 10, reps=3)
     assert e["body"] in (0, 1) and e["tile_cost_s"] > 0
     assert autotune.lookup(dgvol.FORM_F64, 35, 3, tune_missing=False)["body"] == e["body"]
     sizes = {2: 300, 4: 200, 6: 50}
