@@ -59,6 +59,23 @@ __device__ __forceinline__ int tswz(int lane, int s) { return lane ^ ((s & 3) <<
 template <class T>
 __device__ __forceinline__ void store_stream(T* p, const T& v) { __builtin_nontemporal_store(v, p); }
 
+// Raw buffer access: loads past the descriptor's byte range return zero and
+// stores past it are dropped by the hardware range check, so a wave can issue
+// every load and store of a partial tile unconditionally.  With no branches
+// around them the compiler counts the memory operations in flight exactly and
+// waits only for the ones an instruction needs.
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_range(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+__device__ __forceinline__ double buffer_load_f64(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0));
+}
+// streaming (non-temporal) store, as store_stream
+__device__ __forceinline__ void buffer_store_stream_f64(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)byte_off, 0, 2);
+}
+
 // ------------------------------------------------------------------ BF16 split
 
 struct alignas(16) Bf16x8Bits {

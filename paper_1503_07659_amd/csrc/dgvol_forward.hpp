@@ -66,12 +66,9 @@ __device__ __forceinline__ void fwd_f64_staged_single(const FwdArgs<double>& p, 
   using Sh = Shape<NP>;
   constexpr int NFRAG = fwd_table_doubles<NP>();
   constexpr int TILE = 16 * NP;
-  // Where the next tile's u is requested.  Loads and stores share one in-order
-  // completion counter, so a request issued after this tile's output stores
-  // is only usable once those stores have completed; issued before them, it
-  // holds its registers through the products instead.  Measured: early pays
-  // at Np = 56 (matrix-bound), late at Np = 35 (bound by the streams).
-  constexpr bool EARLY = NP >= 56;
+  // The next tile's u is requested after this tile's output stores (late):
+  // the orders that use this form are bound by the streams, and there an early
+  // request, holding its registers through the products, measured slower.
   constexpr int NRAW = (TILE + WAVE - 1) / WAVE;
   double* afr = reinterpret_cast<double*>(lds);
   double* stg_all = reinterpret_cast<double*>(lds + align16(NFRAG * 8));
@@ -119,9 +116,6 @@ __device__ __forceinline__ void fwd_f64_staged_single(const FwdArgs<double>& p, 
 #pragma unroll
     for (int c = 0; c < 9; ++c) gk[c] = valid ? p.G[(int64_t)k * 9 + c] : 0.0;
     wave_sync();
-    if constexpr (EARLY) {
-      if (t + stride < p.ntiles) load_raw(t + stride);
-    }
     f64x4 acc[Sh::MT];
 #pragma unroll
     for (int T = 0; T < Sh::MT; ++T) acc[T] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -161,9 +155,124 @@ __device__ __forceinline__ void fwd_f64_staged_single(const FwdArgs<double>& p, 
       }
       wave_sync();
     }
-    if constexpr (!EARLY) {
-      if (t + stride < p.ntiles) load_raw(t + stride);
+    if (t + stride < p.ntiles) load_raw(t + stride);
+  }
+}
+
+// One tile per wave iteration for the matrix-bound order (Np = 56).  Loads
+// and stores share one in-order completion counter, so a request for the next
+// tile's u issued after this tile's output stores would only be usable once
+// those stores have completed; here it is issued before the products (early)
+// and holds its registers through them.  u and the output move through buffer
+// ranges (no branches around the memory operations), and the next tile is
+// staged at the end of an iteration, so that wait counts exactly the stores
+// issued after the loads instead of waiting for them too.
+template <int NP, int WPB>
+__device__ __forceinline__ void fwd_f64_staged_early(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
+                                                     char* lds) {
+  using Sh = Shape<NP>;
+  constexpr int NFRAG = fwd_table_doubles<NP>();
+  constexpr int TILE = 16 * NP;
+  constexpr int NRAW = (TILE + WAVE - 1) / WAVE;
+  double* afr = reinterpret_cast<double*>(lds);
+  double* stg_all = reinterpret_cast<double*>(lds + align16(NFRAG * 8));
+  for (int e = threadIdx.x; e < NFRAG; e += WAVE * WPB) {
+    const int ts = e >> 6;
+    afr[e] = afrag_f64<NP>(p.D, ts / Sh::KS64, ts % Sh::KS64, e & 63);
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int n = lane & 15, g = lane >> 4;
+  // wave-uniform for certain: the buffer descriptors are built from it
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double* stg = stg_all + wave * TILE;
+  const uint32_t stride = nblk * WPB;
+  uint32_t t = bid * WPB + wave;
+  double raw[NRAW];
+  // tile tt's u through a buffer range of its valid words; past the last tile
+  // the range is empty (zeros, no memory access)
+  auto load_raw = [&](uint32_t tt) {
+    const bool any = tt < p.ntiles;
+    const uint32_t cnt = any ? min(16u, p.ncols - tt * 16) * NP : 0u;
+    const __amdgpu_buffer_rsrc_t r = buffer_range(any ? p.u + (int64_t)tt * TILE : p.u, cnt * 8u);
+#pragma unroll
+    for (int q = 0; q < NRAW; ++q) raw[q] = buffer_load_f64(r, (uint32_t)(lane + WAVE * q) * 8u);
+  };
+  auto stage = [&]() {
+#pragma unroll
+    for (int q = 0; q < NRAW; ++q) {
+      const int x = lane + WAVE * q;
+      if (x < TILE) stg[x] = raw[q];
     }
+    wave_sync();
+  };
+  load_raw(t);
+  stage();
+  for (; t < p.ntiles; t += stride) {
+    const uint32_t col0 = t * 16;
+    const int cnt = (int)min(16u, p.ncols - col0) * NP;
+    double b[Sh::KS64];
+#pragma unroll
+    for (int s = 0; s < Sh::KS64; ++s) {
+      const int j = 4 * s + g;
+      b[s] = j < NP ? stg[n * NP + j] : 0.0;
+    }
+    const uint32_t col = col0 + n;
+    const uint32_t k = (col < p.ncols ? col : 0u) / p.F;
+    double gk[9];  // (columns past the end read element 0; their results are not stored)
+#pragma unroll
+    for (int c = 0; c < 9; ++c) gk[c] = p.G[(int64_t)k * 9 + c];
+    wave_sync();
+    load_raw(t + stride);
+    f64x4 acc[Sh::MT];
+#pragma unroll
+    for (int T = 0; T < Sh::MT; ++T) acc[T] = f64x4{0.0, 0.0, 0.0, 0.0};
+    // A operands are read one k-step ahead of the products that use them, each
+    // read right after a product (else the compiler sinks them all behind the
+    // k-step's products and the next k-step waits on LDS latency).  The wave
+    // raises its priority for the products, so that a wave in its epilogue
+    // does not take issue slots from one in its products.
+    double a_cur[Sh::MT], a_nxt[Sh::MT];
+#pragma unroll
+    for (int T = 0; T < Sh::MT; ++T) a_cur[T] = afr[(T * Sh::KS64) * WAVE + lane];
+    __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+    for (int s = 0; s < Sh::KS64; ++s) {
+#pragma unroll
+      for (int T = 0; T < Sh::MT; ++T) {
+        if (s + 1 < Sh::KS64) a_nxt[T] = afr[(T * Sh::KS64 + s + 1) * WAVE + lane];
+        acc[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[T], b[s], acc[T], 0, 0, 0);
+      }
+#pragma unroll
+      for (int T = 0; T < Sh::MT; ++T) {
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one MFMA,
+        __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // then one LDS read
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int T = 0; T < Sh::MT; ++T) a_cur[T] = a_nxt[T];
+    }
+    __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+#pragma unroll
+      for (int tau = 0; tau < Sh::TRIP; ++tau) {
+        const int i = 4 * tau + g;
+        const int s0 = 3 * tau;
+        const double v = gk[bb] * acc[s0 >> 2][s0 & 3] + gk[3 + bb] * acc[(s0 + 1) >> 2][(s0 + 1) & 3] +
+                         gk[6 + bb] * acc[(s0 + 2) >> 2][(s0 + 2) & 3];
+        if (i < NP) stg[n * NP + i] = v;
+      }
+      wave_sync();
+      const __amdgpu_buffer_rsrc_t ro = buffer_range(p.out + bb * p.plane + (int64_t)col0 * NP, (uint32_t)cnt * 8u);
+#pragma unroll
+      for (int q = 0; q < NRAW; ++q) {
+        const int x = lane + WAVE * q;
+        buffer_store_stream_f64(ro, (uint32_t)x * 8u, stg[min(x, TILE - 1)]);
+      }
+      wave_sync();
+    }
+    stage();  // the next tile's u (its loads were issued before the products)
   }
 }
 
@@ -307,6 +416,8 @@ __device__ __forceinline__ void fwd_f64_staged_body(const FwdArgs<double>& p, ui
                                                     char* lds) {
   if constexpr (staged_tpi<NP>() > 1)
     fwd_f64_staged_multi<NP, WPB>(p, bid, nblk, lds);
+  else if constexpr (NP >= 56)
+    fwd_f64_staged_early<NP, WPB>(p, bid, nblk, lds);
   else
     fwd_f64_staged_single<NP, WPB>(p, bid, nblk, lds);
 }
