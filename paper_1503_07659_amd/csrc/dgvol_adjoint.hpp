@@ -215,7 +215,7 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     fo[r] = tswz(lane, r);
-    tb[r] = (n >> 2) * WAVE + ((16 * (n & 3) + 4 * r + g) ^ ((n >> 2) << 2));
+    tb[r] = (n >> 2) * WAVE + tswz(16 * (n & 3) + 4 * r + g, n >> 2);
   }
   const uint32_t stride = gridDim.x * WPB;
   uint32_t t = blockIdx.x * WPB + wave;

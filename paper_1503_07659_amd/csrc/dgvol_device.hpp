@@ -50,8 +50,12 @@ __device__ __forceinline__ double afragT_f64(const double* __restrict__ D, int T
 template <int NP>
 constexpr int fwd_table_doubles() { return Shape<NP>::MT * Shape<NP>::KS64 * WAVE; }
 
-// XOR swizzle of the A table: entry `lane` of row (T, s) sits at lane ^ ((s & 3) << 2).
-__device__ __forceinline__ int tswz(int lane, int s) { return lane ^ ((s & 3) << 2); }
+// XOR swizzle of the A table: entry `lane` of row (T, s) sits at
+// lane ^ ((s & 3) << 2) ^ ((lane >> 4) & 3).  Both the forward reads (a row,
+// all lanes) and the transposed reads (16 lanes spread over 4 rows and the 4
+// lane groups of a row) then touch 16 distinct 8-byte banks per 16 lanes; with
+// the first term alone the transposed reads were 4-way bank conflicts.
+__device__ __forceinline__ int tswz(int lane, int s) { return lane ^ ((s & 3) << 2) ^ ((lane >> 4) & 3); }
 
 // Output planes are written once and not read again by the launch; streaming
 // (non-temporal) stores measured faster for them on MI355X than ordinary ones

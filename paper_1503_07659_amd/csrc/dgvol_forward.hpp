@@ -54,7 +54,8 @@ constexpr int staged_tpi() { return NP <= 4 ? 4 : (NP <= 20 ? 2 : 1); }
 template <int NP>
 constexpr int staged_wave_doubles() {
   constexpr int TPI = staged_tpi<NP>();
-  return TPI * 16 * NP + (TPI > 1 ? TPI * 16 * 9 : 0);
+  // (Np >= 56: rows padded to an odd stride, see fwd_f64_staged_early)
+  return TPI * 16 * (NP >= 56 ? NP + 1 : NP) + (TPI > 1 ? TPI * 16 * 9 : 0);
 }
 
 template <int NP, int WPB>
@@ -174,6 +175,10 @@ __device__ __forceinline__ void fwd_f64_staged_early(const FwdArgs<double>& p, u
   constexpr int NFRAG = fwd_table_doubles<NP>();
   constexpr int TILE = 16 * NP;
   constexpr int NRAW = (TILE + WAVE - 1) / WAVE;
+  // Odd row stride of the staging buffer: with stride 56 the B-operand reads and
+  // the epilogue writes of the 16 columns met only 2 distinct 8-byte banks
+  // (8-way conflicts; the work took 13 % longer).
+  constexpr int LD = NP + 1;
   double* afr = reinterpret_cast<double*>(lds);
   double* stg_all = reinterpret_cast<double*>(lds + align16(NFRAG * 8));
   for (int e = threadIdx.x; e < NFRAG; e += WAVE * WPB) {
@@ -185,7 +190,7 @@ __device__ __forceinline__ void fwd_f64_staged_early(const FwdArgs<double>& p, u
   const int n = lane & 15, g = lane >> 4;
   // wave-uniform for certain: the buffer descriptors are built from it
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  double* stg = stg_all + wave * TILE;
+  double* stg = stg_all + wave * 16 * LD;
   const uint32_t stride = nblk * WPB;
   uint32_t t = bid * WPB + wave;
   double raw[NRAW];
@@ -202,7 +207,7 @@ __device__ __forceinline__ void fwd_f64_staged_early(const FwdArgs<double>& p, u
 #pragma unroll
     for (int q = 0; q < NRAW; ++q) {
       const int x = lane + WAVE * q;
-      if (x < TILE) stg[x] = raw[q];
+      if (x < TILE) stg[(x / NP) * LD + x % NP] = raw[q];
     }
     wave_sync();
   };
@@ -215,7 +220,7 @@ __device__ __forceinline__ void fwd_f64_staged_early(const FwdArgs<double>& p, u
 #pragma unroll
     for (int s = 0; s < Sh::KS64; ++s) {
       const int j = 4 * s + g;
-      b[s] = j < NP ? stg[n * NP + j] : 0.0;
+      b[s] = j < NP ? stg[n * LD + j] : 0.0;
     }
     const uint32_t col = col0 + n;
     const uint32_t k = (col < p.ncols ? col : 0u) / p.F;
@@ -261,14 +266,15 @@ __device__ __forceinline__ void fwd_f64_staged_early(const FwdArgs<double>& p, u
         const int s0 = 3 * tau;
         const double v = gk[bb] * acc[s0 >> 2][s0 & 3] + gk[3 + bb] * acc[(s0 + 1) >> 2][(s0 + 1) & 3] +
                          gk[6 + bb] * acc[(s0 + 2) >> 2][(s0 + 2) & 3];
-        if (i < NP) stg[n * NP + i] = v;
+        if (i < NP) stg[n * LD + i] = v;
       }
       wave_sync();
       const __amdgpu_buffer_rsrc_t ro = buffer_range(p.out + bb * p.plane + (int64_t)col0 * NP, (uint32_t)cnt * 8u);
 #pragma unroll
       for (int q = 0; q < NRAW; ++q) {
         const int x = lane + WAVE * q;
-        buffer_store_stream_f64(ro, (uint32_t)x * 8u, stg[min(x, TILE - 1)]);
+        const int xc = min(x, TILE - 1);
+        buffer_store_stream_f64(ro, (uint32_t)x * 8u, stg[(xc / NP) * LD + xc % NP]);
       }
       wave_sync();
     }
