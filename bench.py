@@ -97,13 +97,25 @@ def recorded_traffic():
         return None
 
 
-def time_launches(fn, steps, warmup, torch):
-    """Run fn() warmup times, then `steps` times with a HIP event pair around each launch
-    on the current stream (the stream the library launches on).  Returns
-    (ms_per_step over the whole timed region, list of per-launch ms)."""
+# untimed warm-up (wall time) before each secondary measurement
+WARM_MS = 200.0
+
+
+def time_launches(fn, steps, warmup, torch, min_warm_ms=0.0):
+    """Run fn() warmup times (and, with min_warm_ms, further untimed launches until that much
+    wall time has passed: after the GPU has been idle its clocks take tens of milliseconds to
+    ramp up), then `steps` times with a HIP event pair around each launch on the current
+    stream (the stream the library launches on).  Returns (ms_per_step over the whole timed
+    region, list of per-launch ms)."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    if min_warm_ms > 0:
+        t0 = time.perf_counter()
+        while (time.perf_counter() - t0) * 1e3 < min_warm_ms:
+            for _ in range(4):
+                fn()
+            torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
     evs = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     evs[0].record(stream)
@@ -162,14 +174,16 @@ def mixed_orders(torch, dev):
                                  (dgvol.FORM_F32S, "f32s", torch.float32, 4)):
         trip = [tuple(torch.from_numpy(x).to(device=dev, dtype=dt) for x in host[N]) for N in sizes]
         outs = [torch.empty((3,) + tuple(t[2].shape), dtype=dt, device=dev) for t in trip]
-        ms_auto, _ = time_launches(lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs), 20, 3, torch)
+        ms_auto, _ = time_launches(lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs), 20, 3, torch,
+                                   min_warm_ms=WARM_MS)
         bodies, costs = autotune.plan(trip, form)
         tuned = lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs, bodies=bodies, costs=costs)  # noqa: E731
-        ms_tuned, _ = time_launches(tuned, 20, 3, torch)
+        ms_tuned, _ = time_launches(tuned, 20, 3, torch, min_warm_ms=WARM_MS)
         cap = CapturedLaunch(tuned)
-        ms_graph, _ = time_launches(cap.replay, 20, 3, torch)
+        ms_graph, _ = time_launches(cap.replay, 20, 3, torch, min_warm_ms=WARM_MS)
         single = dgvol.dg_volume if form == dgvol.FORM_F64 else dgvol.dg_volume_f32s
-        ms_sep, _ = time_launches(lambda: [single(D, G, u, out=o) for (D, G, u), o in zip(trip, outs)], 20, 3, torch)
+        ms_sep, _ = time_launches(lambda: [single(D, G, u, out=o) for (D, G, u), o in zip(trip, outs)], 20, 3,
+                                  torch, min_warm_ms=WARM_MS)
         peak = FP64_PEAK_TFS * 1e12 if form == dgvol.FORM_F64 else 2.5e15 / 3
         roof = 0.0
         for N, K in sizes.items():
@@ -322,13 +336,15 @@ def main():
 
     # practical streaming ceiling for the same bytes in the same 1 : 3 read : write mix
     n_u = ud.numel()
-    _, per_c = time_launches(lambda: dgvol.dg_stream_calibrate(ud.view(-1), out.view(-1), 3), 10, 2, torch)
+    _, per_c = time_launches(lambda: dgvol.dg_stream_calibrate(ud.view(-1), out.view(-1), 3), 10, 2, torch,
+                             min_warm_ms=WARM_MS)
     ceil_gbs = 4 * n_u * 8 / (float(np.median(per_c)) * 1e-3) / 1e9
-    _, per_1 = time_launches(lambda: dgvol.dg_stream_calibrate(ud.view(-1), out.view(-1)[:n_u], 1), 10, 2, torch)
+    _, per_1 = time_launches(lambda: dgvol.dg_stream_calibrate(ud.view(-1), out.view(-1)[:n_u], 1), 10, 2, torch,
+                             min_warm_ms=WARM_MS)
     copy_gbs = 2 * n_u * 8 / (float(np.median(per_1)) * 1e-3) / 1e9
     # attainable FP64 matrix-core rate: independent MFMA chains from registers
     sink, _ = dgvol.dg_mfma_calibrate(10)
-    _, per_m = time_launches(lambda: dgvol.dg_mfma_calibrate(10000, sink=sink), 5, 1, torch)
+    _, per_m = time_launches(lambda: dgvol.dg_mfma_calibrate(10000, sink=sink), 5, 1, torch, min_warm_ms=WARM_MS)
     cal_flops = dgvol.MFMA_CAL_BLOCKS * 4 * 10000 * 4 * 2048
     mfma_tfs = cal_flops / (float(np.median(per_m)) * 1e-3) / 1e12
     del sink
@@ -366,7 +382,8 @@ def main():
         # chosen precision form at the same shape: FP32 storage, split-BF16 products
         D32, G32, u32 = (torch.from_numpy(x.astype(np.float32)).to(dev) for x in (D, G, u))
         o32 = torch.empty((3, K, F, Np), dtype=torch.float32, device=dev)
-        ms32, per32 = time_launches(lambda: dgvol.dg_volume_f32s(D32, G32, u32, out=o32), 20, 3, torch)
+        ms32, per32 = time_launches(lambda: dgvol.dg_volume_f32s(D32, G32, u32, out=o32), 20, 3, torch,
+                                    min_warm_ms=WARM_MS)
         k32 = float(np.mean(per32))
         forms["f32s_split_bf16_same_workload"] = {
             "GDOF/s": round(dofs / (ms32 * 1e-3) / 1e9, 3), "kernel_ms": round(k32, 5),
@@ -382,18 +399,20 @@ def main():
         G5 = torch.from_numpy(setup_host.geometric_factors(synth.tet_vertices(K5, synth.mesh_seed(5)))).to(dev)
         u5 = torch.from_numpy(synth.fields(K5, F5, Np5, synth.field_seed(5), "uniform")).to(dev)
         o5 = torch.empty((3, K5, F5, Np5), dtype=torch.float64, device=dev)
-        msf, perf = time_launches(lambda: dgvol.dg_volume(D5, G5, u5, out=o5), 20, 3, torch)
+        msf, perf = time_launches(lambda: dgvol.dg_volume(D5, G5, u5, out=o5), 20, 3, torch, min_warm_ms=WARM_MS)
         g5 = 2.0 * o5
         gu5 = torch.empty_like(u5)
         gG5 = torch.empty_like(G5)
-        msa, pera = time_launches(lambda: dgvol.dg_volume_adjoint(D5, G5, u5, g5, gu=gu5, gG=gG5), 20, 3, torch)
+        msa, pera = time_launches(lambda: dgvol.dg_volume_adjoint(D5, G5, u5, g5, gu=gu5, gG=gG5), 20, 3, torch,
+                                  min_warm_ms=WARM_MS)
         ka, kf = float(np.mean(pera)), float(np.mean(perf))
         d5 = K5 * F5 * Np5
         fl_f, fl_a = K5 * fwd_flops_per_element(F5, Np5), K5 * adj_flops_per_element(F5, Np5)
         # cotangent of D for the same cotangent (both kernels of the call are timed)
         gD5 = torch.empty_like(D5)
         wk5 = torch.empty(dgvol.grad_d_workspace_bytes(K5, Np5, F5), dtype=torch.uint8, device=dev)
-        msd, perd = time_launches(lambda: dgvol.dg_volume_grad_d(G5, u5, g5, gD=gD5, work=wk5), 20, 3, torch)
+        msd, perd = time_launches(lambda: dgvol.dg_volume_grad_d(G5, u5, g5, gD=gD5, work=wk5), 20, 3, torch,
+                                  min_warm_ms=WARM_MS)
         kd = float(np.mean(perd))
         forms["fp64_order5_K524288_F3"] = {
             "grad_D_GDOF/s": round(d5 / (msd * 1e-3) / 1e9, 3), "grad_D_call_ms": round(kd, 5),
