@@ -79,6 +79,24 @@ __device__ __forceinline__ double buffer_load_f64(__amdgpu_buffer_rsrc_t r, uint
 __device__ __forceinline__ void buffer_store_stream_f64(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, double v) {
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, (int)byte_off, 0, 2);
 }
+__device__ __forceinline__ float buffer_load_f32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+__device__ __forceinline__ void buffer_store_stream_f32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)byte_off, 0, 2);
+}
+__device__ __forceinline__ double buffer_load_word(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
+  return buffer_load_f64(r, off);
+}
+__device__ __forceinline__ float buffer_load_word(__amdgpu_buffer_rsrc_t r, uint32_t off, float) {
+  return buffer_load_f32(r, off);
+}
+__device__ __forceinline__ void buffer_store_stream_word(__amdgpu_buffer_rsrc_t r, uint32_t off, double v) {
+  buffer_store_stream_f64(r, off, v);
+}
+__device__ __forceinline__ void buffer_store_stream_word(__amdgpu_buffer_rsrc_t r, uint32_t off, float v) {
+  buffer_store_stream_f32(r, off, v);
+}
 
 // ------------------------------------------------------------------ BF16 split
 

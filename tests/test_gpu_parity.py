@@ -66,7 +66,7 @@ def test_forward_orders_and_fields(N, F):
 
 @pytest.mark.parametrize("K,F", [(1, 1), (2, 3), (3, 5), (16, 1), (17, 1), (1, 33)])
 def test_forward_small_and_ragged(K, F):
-    for N in (1, 4, 7):
+    for N in (1, 4, 5, 7):
         _say(f"forward small N={N} K={K} F={F}")
         D, G, u = make_case(N, K, F, 40 + K + F)
         out = host(dgvol.dg_volume(dev(D), dev(G), dev(u)))
@@ -81,16 +81,19 @@ def test_forward_empty():
     assert out.shape == (3, 0, 2, 10)
 
 
-def test_forward_guard_bands_and_determinism():
-    """Writes stay inside out; repeated launches give bitwise identical results."""
-    N, K, F = 4, 999, 5
+@pytest.mark.parametrize("N", [4, 5, 7])
+def test_forward_guard_bands_and_determinism(N):
+    """Writes stay inside out (orders 5 and 7 store through buffer ranges that
+    drop out-of-range lanes); repeated launches give bitwise identical results."""
+    K, F = 999, 5
+    Np = oracle.num_nodes(N)
     _say(f"forward guards N={N} K={K} F={F}")
     D, G, u = make_case(N, K, F, 77, "normal")
-    n = 3 * K * F * 35
+    n = 3 * K * F * Np
     guard = 4096
     buf = torch.full((n + 2 * guard,), 1.25e300, dtype=torch.float64, device="cuda")
     buf[guard:guard + n] = float("nan")
-    out = buf[guard:guard + n].view(3, K, F, 35)
+    out = buf[guard:guard + n].view(3, K, F, Np)
     Dd, Gd, ud = dev(D), dev(G), dev(u)
     dgvol.dg_volume(Dd, Gd, ud, out=out)
     b = host(buf)
