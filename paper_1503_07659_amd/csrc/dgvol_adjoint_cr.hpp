@@ -68,27 +68,30 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
   // staging: thread (cc, rr) owns column cc of the tile and nodes rr + TPC x
   const int cc = tid / S::TPC, rr = tid % S::TPC;
   double r0[S::NX], r1[S::NX], r2[S::NX], rG[9];
+  // Loads from clamped addresses (a tile past the end reads the last column;
+  // its values are not used), so they are unconditional and the compiler's
+  // waits count exactly the memory operations in flight.
   auto load = [&](uint32_t t) __attribute__((always_inline)) {
-    const uint32_t col = t * 16 + cc;
-    const bool v = col < ncols;
+    const uint32_t col = min(t * 16 + cc, ncols - 1);
+    const bool v = t * 16 + cc < ncols;
     const int64_t base = (int64_t)col * NP;
 #pragma unroll
     for (int x = 0; x < S::NX; ++x) {
       const int i = rr + S::TPC * x;
+      const int ic = min(i, NP - 1);
       const bool ok = v && i < NP;
-      r0[x] = ok ? gout[base + i] : 0.0;
-      r1[x] = ok ? gout[plane + base + i] : 0.0;
-      r2[x] = ok ? gout[2 * plane + base + i] : 0.0;
+      const double g0 = gout[base + ic], g1 = gout[plane + base + ic], g2 = gout[2 * plane + base + ic];
+      r0[x] = ok ? g0 : 0.0;
+      r1[x] = ok ? g1 : 0.0;
+      r2[x] = ok ? g2 : 0.0;
     }
-    const int64_t gb = (int64_t)(v ? col / F : 0u) * 9;
+    const int64_t gb = (int64_t)(col / F) * 9;
 #pragma unroll
-    for (int m = 0; m < 9; ++m) rG[m] = v ? G[gb + m] : 0.0;
+    for (int m = 0; m < 9; ++m) rG[m] = G[gb + m];
   };
-  uint32_t t = blockIdx.x;
-  if (t < ntiles) load(t);
-  for (; t < ntiles; t += gridDim.x) {
-    const uint32_t col0 = t * 16;
-    const int cnt = (int)min(16u, ncols - col0) * NP;
+  // W of the loaded tile into the stage; done at the end of an iteration, after
+  // its stores, so the wait for the loads does not cover those stores
+  auto stage = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int x = 0; x < S::NX; ++x) {
       const int i = rr + S::TPC * x;
@@ -98,8 +101,16 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
           ws[cc * S::LDW + a * NP + i] = rG[3 * a] * r0[x] + rG[3 * a + 1] * r1[x] + rG[3 * a + 2] * r2[x];
       }
     }
+  };
+  constexpr int NST = (16 * NP + S::NTH - 1) / S::NTH;  // gu words stored per thread
+  uint32_t t = blockIdx.x;
+  load(min(t, ntiles - 1));
+  stage();
+  for (; t < ntiles; t += gridDim.x) {
+    const uint32_t col0 = t * 16;
+    const int cnt = (int)min(16u, ncols - col0) * NP;
     __syncthreads();
-    if (t + gridDim.x < ntiles) load(t + gridDim.x);
+    load(min(t + gridDim.x, ntiles - 1));
     if (mma) {
       f64x4 acc = f64x4{0.0, 0.0, 0.0, 0.0};
       auto bval = [&](int sp) __attribute__((always_inline)) {
@@ -121,8 +132,13 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
       }
     }
     __syncthreads();
-    double* __restrict__ dst = gu + (int64_t)col0 * NP;
-    for (int x = tid; x < cnt; x += S::NTH) dst[x] = ostg[x];
+    const __amdgpu_buffer_rsrc_t ro = buffer_range(gu + (int64_t)col0 * NP, (uint32_t)cnt * 8u);
+#pragma unroll
+    for (int q = 0; q < NST; ++q) {
+      const int x = tid + S::NTH * q;
+      buffer_store_f64(ro, (uint32_t)x * 8u, ostg[min(x, 16 * NP - 1)]);
+    }
+    stage();
   }
 }
 
@@ -174,7 +190,8 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
 #pragma unroll
     for (int q = 0; q < S::NLD; ++q) {
       const int x = tid + S::NTH * q;
-      ur[q] = x < cnt ? src[x] : 0.0;
+      const double v = src[min(x, cnt - 1)];
+      ur[q] = x < cnt ? v : 0.0;
     }
   };
   uint32_t t = blockIdx.x, sub = 0;
@@ -194,6 +211,22 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
     const uint32_t sub_next = last ? 0u : sub + 1;
     if (t_next < ntiles) load(t_next, sub_next);
     if (mma) {
+      // this lane's gout values, requested before the products (clamped
+      // addresses: unconditional loads; entries outside are zeroed)
+      const bool valid = (uint32_t)n < nc;
+      const int64_t cb = (int64_t)(c0 + (valid ? n : 0)) * NP;
+      double go[4][3];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const int i = 4 * (4 * ch + x) + g;
+        const int ic = min(i, NP - 1);
+        const bool ok = valid && 4 * ch + x < Sh::TRIP && i < NP;
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) {
+          const double v = gout[bb * plane + cb + ic];
+          go[x][bb] = ok ? v : 0.0;
+        }
+      }
       f64x4 acc[3];
 #pragma unroll
       for (int tt = 0; tt < 3; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -212,24 +245,19 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
         bcur = bnxt;
       }
       // P[3a+b] = sum over this lane's nodes of gout_b * (D_a u)
-      const bool valid = (uint32_t)n < nc;
-      const int64_t cb = (int64_t)(c0 + (valid ? n : 0)) * NP;
       double P[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) P[c] = 0.0;
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
-        const int tau = 4 * ch + x;
-        const int i = 4 * tau + g;
-        if (tau < Sh::TRIP && i < NP && valid) {
-          const double g0 = gout[cb + i], g1 = gout[plane + cb + i], g2 = gout[2 * plane + cb + i];
+        if (4 * ch + x < Sh::TRIP) {
 #pragma unroll
           for (int a = 0; a < 3; ++a) {
             const int l = 3 * x + a;
             const double R = acc[l >> 2][l & 3];
-            P[3 * a] += g0 * R;
-            P[3 * a + 1] += g1 * R;
-            P[3 * a + 2] += g2 * R;
+            P[3 * a] += go[x][0] * R;
+            P[3 * a + 1] += go[x][1] * R;
+            P[3 * a + 2] += go[x][2] * R;
           }
         }
       }
