@@ -264,9 +264,9 @@ static double tile_cost_estimate(int form, int Np, uint32_t F) {
     case 10: eff = form == DG_FORM_F64 ? 0.70 : 0.68; break;
     case 20: eff = form == DG_FORM_F64 ? 0.73 : 0.68; break;
     case 35: eff = form == DG_FORM_F64 ? 0.58 : 0.68; break;
-    case 56: eff = form == DG_FORM_F64 ? 0.42 : 0.78; break;
-    case 84: eff = form == DG_FORM_F64 ? 0.40 : 0.68; break;
-    default: eff = form == DG_FORM_F64 ? 0.55 : 0.42; break;  // Np = 120
+    case 56: eff = form == DG_FORM_F64 ? 0.63 : 0.78; break;
+    case 84: eff = form == DG_FORM_F64 ? 0.46 : 0.68; break;
+    default: eff = form == DG_FORM_F64 ? 0.67 : 0.50; break;  // Np = 120
   }
   return std::max(bytes / bw, flops / peak) / eff;
 }
