@@ -159,16 +159,18 @@ typedef struct dg_group {
   void *out;           /* [3][K][F][Np], written */
   double cost;         /* measured cost of one 16-column tile, any unit common to the
                           batch, used to split workgroups between groups; <= 0 selects
-                          the library's roofline estimate */
+                          the library's estimate (spec roofline time of a tile over the
+                          fraction of it the order's default body reaches) */
 } dg_group;
 
 /*
  * Forward volume derivative of up to DG_MAX_GROUPS element groups of
  * possibly different orders, sharing F, in ONE persistent kernel launch.
  * `groups` is a host array of `ngroups` descriptors; it is read during the
- * call only.  Workgroups are split between groups in proportion to
- * cost x tiles (a static split: the launch needs no device-side state and can
- * be captured in a HIP graph).  Each group's out is exactly what dg_volume /
+ * call only.  The resident workgroups are split between groups by cost x tiles,
+ * so that the largest cost per workgroup is as small as possible (every group
+ * gets at least one; Jefferson apportionment).  The split is static: the launch
+ * needs no device-side state and can be captured in a HIP graph.  Each group's out is exactly what dg_volume /
  * dg_volume_f32s would write for that group alone.
  * Errors: DG_EINVAL (ngroups outside 0..DG_MAX_GROUPS, F < 1, NULL groups
  * with ngroups > 0, a group failing the dg_volume argument checks),
