@@ -14,7 +14,8 @@
 //    once per workgroup (the paper's precompute of a repeatedly fetched
 //    operand into on-chip storage, Section 4.3); every wave owns whole
 //    16-column tiles and moves u in and each output plane out through one LDS
-//    buffer of 16 x Np words, so all global accesses are contiguous runs.
+//    buffer of 16 x Np words (rows padded to an odd stride at Np = 56), so all
+//    global accesses are contiguous runs.
 //  * chunk-register (matrix-core-bound orders, D too large for LDS): the
 //    workgroup shares a run of 16-column tiles per iteration; wave w keeps the
 //    A operands of output chunk w (3 tiles) in registers for the whole launch;
