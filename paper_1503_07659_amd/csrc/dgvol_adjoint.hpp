@@ -272,20 +272,18 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
     for (int c = 0; c < 9; ++c) P[c] = 0.0;
 #pragma unroll
     for (int ch = 0; ch < Sh::NCHUNK; ++ch) {
-      double go[4][3];
+      // this lane's gout values for the chunk, requested before the forward
+      // product (clamped addresses: unconditional loads); zeroed outside only
+      // where they are used, after the product, so the wait for them does not
+      // land in its first k-step
+      double gor[4][3];
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
-        const int tau = 4 * ch + x;
-        if (tau < Sh::TRIP) {
-          const int i = 4 * tau + g;
-          const bool ok = valid && i < NP;
+        const int i = 4 * (4 * ch + x) + g;
 #pragma unroll
-          for (int bb = 0; bb < 3; ++bb) {
-            const double v = goc[bb * plane + min(i, NP - 1)];
-            go[x][bb] = ok ? v : 0.0;
-          }
-        }
+        for (int bb = 0; bb < 3; ++bb) gor[x][bb] = 4 * ch + x < Sh::TRIP ? goc[bb * plane + min(i, NP - 1)] : 0.0;
       }
+      __builtin_amdgcn_sched_barrier(0);
       f64x4 acc[3];
 #pragma unroll
       for (int tt = 0; tt < 3; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -302,6 +300,13 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
         }
         __builtin_amdgcn_sched_barrier(0);
       }
+      double go[4][3];
+#pragma unroll
+      for (int x = 0; x < 4; ++x) {
+        const bool ok = valid && 4 * (4 * ch + x) + g < NP;
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb) go[x][bb] = ok ? gor[x][bb] : 0.0;
+      }
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
         const int tau = 4 * ch + x;
@@ -315,17 +320,42 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
           }
         }
       }
+      // W of the chunk's 12 slots at once, then the transposed product with its
+      // operands read one slot ahead (one read after each product)
+      double wv[12];
+      {
+        double gl[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) gl[c] = ge[c];
+#pragma unroll
+        for (int sl = 0; sl < 12; ++sl) {
+          const int x = sl / 3, a = sl % 3;
+          wv[sl] = gl[3 * a] * go[x][0] + gl[3 * a + 1] * go[x][1] + gl[3 * a + 2] * go[x][2];
+        }
+      }
+      auto top = [&](int sp, int tj) { return afr[((sp >> 2) * KS + 4 * tj) * WAVE + tb[sp & 3]]; };
+      double tc[Sh::MTJ], tn[Sh::MTJ];
+#pragma unroll
+      for (int tj = 0; tj < Sh::MTJ; ++tj) tc[tj] = top(12 * ch, tj);
+      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int sl = 0; sl < 12; ++sl) {
         const int sp = 12 * ch + sl;
         if (sp < Sh::SLOTS) {
-          const int x = sl / 3, a = sl % 3;
-          const double wv = ge[3 * a] * go[x][0] + ge[3 * a + 1] * go[x][1] + ge[3 * a + 2] * go[x][2];
+          const bool more = sl + 1 < 12 && sp + 1 < Sh::SLOTS;
 #pragma unroll
-          for (int tj = 0; tj < Sh::MTJ; ++tj)
-            accj[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[((sp >> 2) * KS + 4 * tj) * WAVE + tb[sp & 3]],
-                                                            wv, accj[tj], 0, 0, 0);
+          for (int tj = 0; tj < Sh::MTJ; ++tj) {
+            if (more) tn[tj] = top(sp + 1, tj);
+            accj[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(tc[tj], wv[sl], accj[tj], 0, 0, 0);
+          }
+#pragma unroll
+          for (int tj = 0; tj < Sh::MTJ; ++tj) {
+            __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+            __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+          }
           __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+          for (int tj = 0; tj < Sh::MTJ; ++tj) tc[tj] = tn[tj];
         }
       }
     }
