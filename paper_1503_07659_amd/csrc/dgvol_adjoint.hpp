@@ -223,25 +223,43 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   // run of G), loaded one tile ahead
   constexpr int NGR = (16 * 9 + WAVE - 1) / WAVE;
   double raw[NRAW], graw[NGR];
+  // At Np = 56 the kernel sits at the register limit; there u, G and gu move
+  // through buffer ranges (past the range: zero loads, dropped stores; empty
+  // past the last tile), so no branch surrounds a memory operation.  The
+  // compiler then allocates without spilling (measured -15 %).  At the lower
+  // orders the guarded form measured 1-4 % faster.
+  constexpr bool BUF = NP >= 56;
   auto load_raw = [&](uint32_t tt) __attribute__((always_inline)) {
     const uint32_t kk0 = tt * E;
-    const uint32_t ne = min(E, K - kk0);
-    const double* __restrict__ src = u + (int64_t)kk0 * F * NP;
-    const int cnt = (int)(ne * F) * NP;
+    if constexpr (BUF) {
+      const bool any = tt < ntiles;
+      const uint32_t ne = any ? min(E, K - kk0) : 0u;
+      const __amdgpu_buffer_rsrc_t ru = buffer_range(any ? u + (int64_t)kk0 * F * NP : u, ne * F * NP * 8u);
 #pragma unroll
-    for (int q = 0; q < NRAW; ++q) {
-      const int x = lane + WAVE * q;
-      const double v = src[min(x, cnt - 1)];
-      raw[q] = x < cnt ? v : 0.0;
-    }
-    const double* __restrict__ gsrc = G + (int64_t)kk0 * 9;
+      for (int q = 0; q < NRAW; ++q) raw[q] = buffer_load_f64(ru, (uint32_t)(lane + WAVE * q) * 8u);
+      const __amdgpu_buffer_rsrc_t rg = buffer_range(any ? G + (int64_t)kk0 * 9 : G, ne * 9 * 8u);
 #pragma unroll
-    for (int q = 0; q < NGR; ++q) {
-      const int x = lane + WAVE * q;
-      graw[q] = x < (int)ne * 9 ? gsrc[x] : 0.0;
+      for (int q = 0; q < NGR; ++q) graw[q] = buffer_load_f64(rg, (uint32_t)(lane + WAVE * q) * 8u);
+    } else {
+      if (tt >= ntiles) return;
+      const uint32_t ne = min(E, K - kk0);
+      const double* __restrict__ src = u + (int64_t)kk0 * F * NP;
+      const int cnt = (int)(ne * F) * NP;
+#pragma unroll
+      for (int q = 0; q < NRAW; ++q) {
+        const int x = lane + WAVE * q;
+        const double v = src[min(x, cnt - 1)];
+        raw[q] = x < cnt ? v : 0.0;
+      }
+      const double* __restrict__ gsrc = G + (int64_t)kk0 * 9;
+#pragma unroll
+      for (int q = 0; q < NGR; ++q) {
+        const int x = lane + WAVE * q;
+        graw[q] = x < (int)ne * 9 ? gsrc[x] : 0.0;
+      }
     }
   };
-  if (t < ntiles) load_raw(t);
+  load_raw(t);
   for (; t < ntiles; t += stride) {
     const uint32_t k0 = t * E;
     const uint32_t ne = min(E, K - k0);
@@ -370,11 +388,21 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
       }
     }
     wave_sync();
-    double* __restrict__ gdst = gu + (int64_t)col0 * NP;
+    if constexpr (BUF) {
+      const __amdgpu_buffer_rsrc_t rgu = buffer_range(gu + (int64_t)col0 * NP, (uint32_t)cnt * 8u);
 #pragma unroll
-    for (int q = 0; q < NRAW; ++q) {
-      const int x = lane + WAVE * q;
-      if (x < cnt) gdst[x] = stg[(x / NP) * LD + (x % NP)];
+      for (int q = 0; q < NRAW; ++q) {
+        const int x = lane + WAVE * q;
+        const int xc = min(x, TILE - 1);
+        buffer_store_f64(rgu, (uint32_t)x * 8u, stg[(xc / NP) * LD + (xc % NP)]);
+      }
+    } else {
+      double* __restrict__ gdst = gu + (int64_t)col0 * NP;
+#pragma unroll
+      for (int q = 0; q < NRAW; ++q) {
+        const int x = lane + WAVE * q;
+        if (x < cnt) gdst[x] = stg[(x / NP) * LD + (x % NP)];
+      }
     }
     // gG: four lane groups, then the F columns of each element, in a fixed order
 #pragma unroll
@@ -396,7 +424,7 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
       }
     }
     wave_sync();
-    if (t + stride < ntiles) load_raw(t + stride);
+    load_raw(t + stride);
   }
 }
 
