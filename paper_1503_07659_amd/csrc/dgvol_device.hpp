@@ -88,6 +88,22 @@ __device__ __forceinline__ float buffer_load_f32(__amdgpu_buffer_rsrc_t r, uint3
 __device__ __forceinline__ void buffer_store_stream_f32(__amdgpu_buffer_rsrc_t r, uint32_t byte_off, float v) {
   __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned int, v), r, (int)byte_off, 0, 2);
 }
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+// VEC consecutive words as one 16-byte access (VEC * sizeof(T) == 16)
+template <typename T, int VEC>
+struct WordVec {
+  T v[VEC];
+};
+template <typename T, int VEC>
+__device__ __forceinline__ WordVec<T, VEC> buffer_load_vec(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  static_assert(VEC * sizeof(T) == 16, "16-byte access");
+  return __builtin_bit_cast(WordVec<T, VEC>, __builtin_amdgcn_raw_buffer_load_b128(r, (int)byte_off, 0, 0));
+}
+template <typename T, int VEC>
+__device__ __forceinline__ void buffer_store_stream_vec(__amdgpu_buffer_rsrc_t r, uint32_t byte_off,
+                                                        const WordVec<T, VEC>& x) {
+  __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, x), r, (int)byte_off, 0, 2);
+}
 __device__ __forceinline__ double buffer_load_word(__amdgpu_buffer_rsrc_t r, uint32_t off, double) {
   return buffer_load_f64(r, off);
 }

@@ -471,9 +471,9 @@ constexpr int fwd_f64_chunkreg_lds() { return chunk_lds<NP, 8>(); }
 // compiler's waits count exactly the operations in flight; with conditional
 // loads and stores every wait had become a wait for everything, including the
 // previous iteration's stores (order 7 took 13 % longer).
-template <typename T, int NP, int WPB, int KS, typename ChunkFn>
-__device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid, uint32_t nblk, char* lds,
-                                              ChunkFn&& chunk) {
+template <typename T, int NP, int WPB, int KS, int VEC, typename ChunkFn>
+__device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t bid, uint32_t nblk, char* lds,
+                                                  ChunkFn&& chunk) {
   constexpr int WORD = sizeof(T);
   constexpr int TPW = chunk_tpw<NP, WORD>();
   constexpr int LD = chunk_ld<NP, WORD>();
@@ -481,7 +481,8 @@ __device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid,
   constexpr int OLD = chunk_old<NP, WORD>();
   constexpr int OSUP = TPW * 16 * OLD;      // words of one plane of the output tile
   constexpr int NT = WAVE * WPB;
-  constexpr int NLD = (SUP + NT - 1) / NT;  // u words loaded per thread per iteration
+  static_assert(NP % VEC == 0, "a vector never crosses a column");
+  constexpr int NLD = (SUP / VEC + NT - 1) / NT;  // u vectors loaded per thread per iteration
   constexpr int GMAX = TPW * 16 * 9;        // geometric-factor words of at most TPW*16 elements
   constexpr int NG = (GMAX + NT - 1) / NT;  // G words loaded per thread per iteration
   T* us = reinterpret_cast<T*>(lds);
@@ -489,18 +490,27 @@ __device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid,
   T* gs = reinterpret_cast<T*>(lds + align16(TPW * 16 * LD * WORD + 32) + align16(3 * OSUP * WORD));
   const int tid = threadIdx.x;
   const uint32_t nsup = (p.ntiles + TPW - 1) / TPW;
-  T ur[NLD];
+  T ur[NLD][VEC];
   T gr[NG];
   // run s's u and geometric factors through buffer ranges of their valid words
   // (empty past the last run: zeros, no memory access), so the loads are
-  // unconditional
+  // unconditional; a vector lies wholly inside or outside a range
   auto load = [&](uint32_t s) {
     const bool any = s < nsup;
     const uint32_t c0 = s * TPW * 16;
     const uint32_t ncl = any ? min((uint32_t)(TPW * 16), p.ncols - c0) : 0u;
     const __amdgpu_buffer_rsrc_t ru = buffer_range(any ? p.u + (int64_t)c0 * NP : p.u, ncl * NP * WORD);
 #pragma unroll
-    for (int q = 0; q < NLD; ++q) ur[q] = buffer_load_word(ru, (uint32_t)(tid + NT * q) * WORD, T());
+    for (int q = 0; q < NLD; ++q) {
+      const uint32_t off = (uint32_t)(tid + NT * q) * (VEC * WORD);
+      if constexpr (VEC == 1) {
+        ur[q][0] = buffer_load_word(ru, off, T());
+      } else {
+        const WordVec<T, VEC> v = buffer_load_vec<T, VEC>(ru, off);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) ur[q][e] = v.v[e];
+      }
+    }
     const uint32_t k_lo = any ? c0 / p.F : 0u;
     const uint32_t nk = any ? (c0 + ncl - 1) / p.F - k_lo + 1 : 0u;
     const __amdgpu_buffer_rsrc_t rg = buffer_range(any ? p.G + (int64_t)k_lo * 9 : p.G, nk * 9 * WORD);
@@ -512,8 +522,11 @@ __device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid,
   auto stage = [&]() {
 #pragma unroll
     for (int q = 0; q < NLD; ++q) {
-      const int x = tid + NT * q;
-      if (x < SUP) us[(x / NP) * LD + (x % NP)] = ur[q];
+      const int x0 = (tid + NT * q) * VEC;
+      if (x0 < SUP) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) us[(x0 / NP) * LD + (x0 % NP) + e] = ur[q][e];
+      }
     }
 #pragma unroll
     for (int q = 0; q < NG; ++q)
@@ -535,13 +548,38 @@ __device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid,
       const __amdgpu_buffer_rsrc_t ro = buffer_range(p.out + bb * p.plane + (int64_t)col0 * NP, (uint32_t)cnt * WORD);
 #pragma unroll
       for (int q = 0; q < NLD; ++q) {
-        const int x = tid + NT * q;
-        const int xc = min(x, SUP - 1);
-        buffer_store_stream_word(ro, (uint32_t)x * WORD, ostg[bb * OSUP + (xc / NP) * OLD + (xc % NP)]);
+        const int x0 = (tid + NT * q) * VEC;
+        const int xc = min(x0, SUP - VEC);
+        const T* src = ostg + bb * OSUP + (xc / NP) * OLD + (xc % NP);
+        if constexpr (VEC == 1) {
+          buffer_store_stream_word(ro, (uint32_t)x0 * WORD, src[0]);
+        } else {
+          WordVec<T, VEC> v;
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) v.v[e] = src[e];
+          buffer_store_stream_vec<T, VEC>(ro, (uint32_t)x0 * WORD, v);
+        }
       }
     }
     stage();
   }
+}
+
+// FP64: pairs of doubles (16-byte accesses) where a column is a whole number
+// of them and u, out start 16-byte aligned (planes then are too); single words
+// otherwise.  Measured: pairs -4 % (order 7) and -5 % (order 6); four-float
+// vectors made the split-BF16 body 2-3 % slower, so it moves single words.
+template <typename T, int NP, int WPB, int KS, typename ChunkFn>
+__device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid, uint32_t nblk, char* lds,
+                                              ChunkFn&& chunk) {
+  constexpr int V = sizeof(T) == 8 ? 2 : 1;
+  if constexpr (V > 1 && NP % V == 0) {
+    if ((((uintptr_t)p.u | (uintptr_t)p.out) & 15u) == 0) {
+      chunkreg_loop_vec<T, NP, WPB, KS, V>(p, bid, nblk, lds, chunk);
+      return;
+    }
+  }
+  chunkreg_loop_vec<T, NP, WPB, KS, 1>(p, bid, nblk, lds, chunk);
 }
 
 template <int NP, int WPB>

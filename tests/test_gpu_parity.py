@@ -81,16 +81,18 @@ def test_forward_empty():
     assert out.shape == (3, 0, 2, 10)
 
 
-@pytest.mark.parametrize("N", [4, 5, 7])
-def test_forward_guard_bands_and_determinism(N):
+@pytest.mark.parametrize("N,shift", [(4, 0), (5, 0), (7, 0), (7, 1)])
+def test_forward_guard_bands_and_determinism(N, shift):
     """Writes stay inside out (orders 5 and 7 store through buffer ranges that
-    drop out-of-range lanes); repeated launches give bitwise identical results."""
+    drop out-of-range lanes); repeated launches give bitwise identical results.
+    shift = 1 moves out off 16-byte alignment (the single-word path of the
+    chunk-register body)."""
     K, F = 999, 5
     Np = oracle.num_nodes(N)
-    _say(f"forward guards N={N} K={K} F={F}")
+    _say(f"forward guards N={N} K={K} F={F} shift={shift}")
     D, G, u = make_case(N, K, F, 77, "normal")
     n = 3 * K * F * Np
-    guard = 4096
+    guard = 4096 + shift
     buf = torch.full((n + 2 * guard,), 1.25e300, dtype=torch.float64, device="cuda")
     buf[guard:guard + n] = float("nan")
     out = buf[guard:guard + n].view(3, K, F, Np)
