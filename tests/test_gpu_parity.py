@@ -167,6 +167,28 @@ def test_adjoint_small(K, F):
         _check_adjoint(D, G, u, gout, host(gu), host(gG))
 
 
+@pytest.mark.parametrize("N", [3, 5, 7])
+def test_adjoint_guard_bands(N):
+    """gu and gG are written only inside their views (order 5 stores gu through
+    buffer ranges that drop out-of-range lanes; orders 6-7 run two passes)."""
+    K, F = 301, 3
+    Np = oracle.num_nodes(N)
+    _say(f"adjoint guards N={N} K={K} F={F}")
+    D, G, u = make_case(N, K, F, 88, "normal")
+    gout = np.random.default_rng(89).standard_normal((3, K, F, Np))
+    guard = 1024
+    nu, ng = K * F * Np, K * 9
+    bu = torch.full((nu + 2 * guard,), 1.25e300, dtype=torch.float64, device="cuda")
+    bg = torch.full((ng + 2 * guard,), 1.25e300, dtype=torch.float64, device="cuda")
+    gu = bu[guard:guard + nu].view(K, F, Np)
+    gG = bg[guard:guard + ng].view(K, 9)
+    dgvol.dg_volume_adjoint(dev(D), dev(G), dev(u), dev(gout), gu=gu, gG=gG)
+    hu, hg = host(bu), host(bg)
+    assert (hu[:guard] == 1.25e300).all() and (hu[guard + nu:] == 1.25e300).all()
+    assert (hg[:guard] == 1.25e300).all() and (hg[guard + ng:] == 1.25e300).all()
+    _check_adjoint(D, G, u, gout, host(gu), host(gG))
+
+
 @pytest.mark.parametrize("N,K,F", [(5, 3000, 3), (5, 700, 20), (6, 900, 3), (7, 600, 3), (7, 300, 20)])
 def test_adjoint_deterministic(N, K, F):
     """Every adjoint path (staged, general, two-pass) gives the same bits on
