@@ -307,7 +307,7 @@ __device__ __forceinline__ void fwd_f64_staged_multi(const FwdArgs<double>& p, u
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
-  const uint32_t wave = threadIdx.x >> 6;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* su = reinterpret_cast<double*>(lds + align16(NFRAG * 8)) + wave * staged_wave_doubles<NP>();
   double* sg = su + RUN;
   const uint32_t nrun = (p.ntiles + TPI - 1) / TPI;
@@ -321,32 +321,23 @@ __device__ __forceinline__ void fwd_f64_staged_multi(const FwdArgs<double>& p, u
     e0 = c0 / p.F;
     ng = (int)(c1 / p.F - e0 + 1) * 9;
   };
+  // run tt's u and G through buffer ranges of their valid words (empty past
+  // the last run), so the loads are unconditional
   auto load_run = [&](uint32_t tt) __attribute__((always_inline)) {
+    const bool any = tt < nrun;
     const uint32_t c0 = tt * (16 * TPI);
-    const double* __restrict__ src = p.u + (int64_t)c0 * NP;
-    const int cnt = (int)min(16u * TPI, p.ncols - c0) * NP;
+    const uint32_t cnt = any ? min(16u * TPI, p.ncols - c0) * NP : 0u;
+    const __amdgpu_buffer_rsrc_t ru = buffer_range(any ? p.u + (int64_t)c0 * NP : p.u, cnt * 8u);
 #pragma unroll
-    for (int q = 0; q < NRAW; ++q) {
-      const int x = lane + WAVE * q;
-      raw[q] = x < cnt ? src[x] : 0.0;
-    }
-    uint32_t e0;
-    int ng;
-    run_elems(tt, e0, ng);
-    const double* __restrict__ gsrc = p.G + (int64_t)e0 * 9;
+    for (int q = 0; q < NRAW; ++q) raw[q] = buffer_load_f64(ru, (uint32_t)(lane + WAVE * q) * 8u);
+    uint32_t e0 = 0;
+    int ng = 0;
+    if (any) run_elems(tt, e0, ng);
+    const __amdgpu_buffer_rsrc_t rg = buffer_range(p.G + (int64_t)e0 * 9, (uint32_t)ng * 8u);
 #pragma unroll
-    for (int q = 0; q < NGR; ++q) {
-      const int x = lane + WAVE * q;
-      graw[q] = x < ng ? gsrc[x] : 0.0;
-    }
+    for (int q = 0; q < NGR; ++q) graw[q] = buffer_load_f64(rg, (uint32_t)(lane + WAVE * q) * 8u);
   };
-  if (t < nrun) load_run(t);
-  for (; t < nrun; t += stride) {
-    const uint32_t col0 = t * (16 * TPI);
-    const int cnt = (int)min(16u * TPI, p.ncols - col0) * NP;
-    uint32_t e0;
-    int ng;
-    run_elems(t, e0, ng);
+  auto stage = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int q = 0; q < NRAW; ++q) {
       const int x = lane + WAVE * q;
@@ -358,6 +349,15 @@ __device__ __forceinline__ void fwd_f64_staged_multi(const FwdArgs<double>& p, u
       if (x < GW) sg[x] = graw[q];
     }
     wave_sync();
+  };
+  load_run(t);
+  stage();
+  for (; t < nrun; t += stride) {
+    const uint32_t col0 = t * (16 * TPI);
+    const int cnt = (int)min(16u * TPI, p.ncols - col0) * NP;
+    uint32_t e0;
+    int ng;
+    run_elems(t, e0, ng);
     double b[TPI][Sh::KS64];
 #pragma unroll
     for (int r = 0; r < TPI; ++r) {
@@ -368,7 +368,7 @@ __device__ __forceinline__ void fwd_f64_staged_multi(const FwdArgs<double>& p, u
       }
     }
     wave_sync();
-    if (t + stride < nrun) load_run(t + stride);
+    load_run(t + stride);
     f64x4 acc[TPI][Sh::MT];
 #pragma unroll
     for (int r = 0; r < TPI; ++r) {
@@ -406,14 +406,15 @@ __device__ __forceinline__ void fwd_f64_staged_multi(const FwdArgs<double>& p, u
         }
       }
       wave_sync();
-      double* __restrict__ ob = p.out + bb * p.plane + (int64_t)col0 * NP;
+      const __amdgpu_buffer_rsrc_t ro = buffer_range(p.out + bb * p.plane + (int64_t)col0 * NP, (uint32_t)cnt * 8u);
 #pragma unroll
       for (int q = 0; q < NRAW; ++q) {
         const int x = lane + WAVE * q;
-        if (x < cnt) store_stream(&ob[x], su[x]);
+        buffer_store_stream_f64(ro, (uint32_t)x * 8u, su[min(x, RUN - 1)]);
       }
       wave_sync();
     }
+    stage();  // the next run (its loads were issued before the products)
     (void)ng;
   }
 }
