@@ -451,11 +451,24 @@ constexpr int chunk_old() { return WORD == 8 ? NP + 2 : ((NP + 3) / 8) * 8 + 4; 
 template <int NP, int WORD>
 constexpr int chunk_tpw() { return WORD == 4 ? 4 : (NP >= 120 ? 1 : 2); }
 
+// Split-BF16: u is staged already split, as BF16 hi and lo planes with this
+// row stride (elements): every k-step's 32 entries plus 8, so a row is 16
+// modulo 32 bytes and the 16 lanes of a 16-byte read group start on distinct
+// banks; the entries past Np stay zero.
+template <int NP>
+constexpr int chunk_ldb() { return Shape<NP>::KS16 * 32 + 8; }
+
+// Bytes of the staged u of one iteration.
+template <int NP, int WORD>
+constexpr int chunk_us_bytes() {
+  constexpr int TPW = chunk_tpw<NP, WORD>();
+  return WORD == 8 ? TPW * 16 * chunk_ld<NP, WORD>() * WORD : 2 * TPW * 16 * chunk_ldb<NP>() * 2;
+}
+
 template <int NP, int WORD>
 constexpr int chunk_lds() {
   constexpr int TPW = chunk_tpw<NP, WORD>();
-  // (+32 bytes: the FP32 operand reads of the last row may run past it by up to 7 words)
-  return align16(TPW * 16 * chunk_ld<NP, WORD>() * WORD + 32) + align16(3 * TPW * 16 * chunk_old<NP, WORD>() * WORD) +
+  return align16(chunk_us_bytes<NP, WORD>()) + align16(3 * TPW * 16 * chunk_old<NP, WORD>() * WORD) +
          TPW * 16 * 9 * WORD;
 }
 
@@ -472,9 +485,9 @@ constexpr int fwd_f64_chunkreg_lds() { return chunk_lds<NP, 8>(); }
 // compiler's waits count exactly the operations in flight; with conditional
 // loads and stores every wait had become a wait for everything, including the
 // previous iteration's stores (order 7 took 13 % longer).
-template <typename T, int NP, int WPB, int KS, int VEC, typename ChunkFn>
+template <typename T, int NP, int WPB, int KS, int VEC, typename ChunkFn, typename PutU>
 __device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t bid, uint32_t nblk, char* lds,
-                                                  ChunkFn&& chunk) {
+                                                  ChunkFn&& chunk, PutU&& put_u) {
   constexpr int WORD = sizeof(T);
   constexpr int TPW = chunk_tpw<NP, WORD>();
   constexpr int LD = chunk_ld<NP, WORD>();
@@ -486,9 +499,10 @@ __device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t 
   constexpr int NLD = (SUP / VEC + NT - 1) / NT;  // u vectors loaded per thread per iteration
   constexpr int GMAX = TPW * 16 * 9;        // geometric-factor words of at most TPW*16 elements
   constexpr int NG = (GMAX + NT - 1) / NT;  // G words loaded per thread per iteration
-  T* us = reinterpret_cast<T*>(lds);
-  T* ostg = reinterpret_cast<T*>(lds + align16(TPW * 16 * LD * WORD + 32));
-  T* gs = reinterpret_cast<T*>(lds + align16(TPW * 16 * LD * WORD + 32) + align16(3 * OSUP * WORD));
+  (void)LD;
+  char* us = lds;  // laid out by put_u (the body's staging of one u word)
+  T* ostg = reinterpret_cast<T*>(lds + align16(chunk_us_bytes<NP, WORD>()));
+  T* gs = reinterpret_cast<T*>(lds + align16(chunk_us_bytes<NP, WORD>()) + align16(3 * OSUP * WORD));
   const int tid = threadIdx.x;
   const uint32_t nsup = (p.ntiles + TPW - 1) / TPW;
   T ur[NLD][VEC];
@@ -526,7 +540,7 @@ __device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t 
       const int x0 = (tid + NT * q) * VEC;
       if (x0 < SUP) {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) us[(x0 / NP) * LD + (x0 % NP) + e] = ur[q][e];
+        for (int e = 0; e < VEC; ++e) put_u(us, x0 / NP, x0 % NP + e, ur[q][e]);
       }
     }
 #pragma unroll
@@ -570,17 +584,17 @@ __device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t 
 // of them and u, out start 16-byte aligned (planes then are too); single words
 // otherwise.  Measured: pairs -4 % (order 7) and -5 % (order 6); four-float
 // vectors made the split-BF16 body 2-3 % slower, so it moves single words.
-template <typename T, int NP, int WPB, int KS, typename ChunkFn>
+template <typename T, int NP, int WPB, int KS, typename ChunkFn, typename PutU>
 __device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid, uint32_t nblk, char* lds,
-                                              ChunkFn&& chunk) {
+                                              ChunkFn&& chunk, PutU&& put_u) {
   constexpr int V = sizeof(T) == 8 ? 2 : 1;
   if constexpr (V > 1 && NP % V == 0) {
     if ((((uintptr_t)p.u | (uintptr_t)p.out) & 15u) == 0) {
-      chunkreg_loop_vec<T, NP, WPB, KS, V>(p, bid, nblk, lds, chunk);
+      chunkreg_loop_vec<T, NP, WPB, KS, V>(p, bid, nblk, lds, chunk, put_u);
       return;
     }
   }
-  chunkreg_loop_vec<T, NP, WPB, KS, 1>(p, bid, nblk, lds, chunk);
+  chunkreg_loop_vec<T, NP, WPB, KS, 1>(p, bid, nblk, lds, chunk, put_u);
 }
 
 template <int NP, int WPB>
@@ -606,8 +620,10 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
 #pragma unroll
     for (int s = 0; s < KS; ++s) areg[tt][s] = (mma && T < Sh::MT) ? afrag_f64<NP>(p.D, T, s, lane) : 0.0;
   }
-  auto chunk = [&](const double* us, double* ostg, const double* gs, uint32_t col0, uint32_t k_lo) {
+  auto put_u = [](char* us, int c, int i, double v) { reinterpret_cast<double*>(us)[c * LD + i] = v; };
+  auto chunk = [&](const char* usb, double* ostg, const double* gs, uint32_t col0, uint32_t k_lo) {
     if (!mma) return;
+    const double* us = reinterpret_cast<const double*>(usb);
 #pragma unroll
     for (int tp = 0; tp < TPW; ++tp) {
       const int cl = tp * 16 + n;  // column within the super-tile
@@ -645,7 +661,7 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
       }
     }
   };
-  chunkreg_loop<double, NP, WPB, KS>(p, bid, nblk, lds, chunk);
+  chunkreg_loop<double, NP, WPB, KS>(p, bid, nblk, lds, chunk, put_u);
 }
 
 }  // namespace dgvol

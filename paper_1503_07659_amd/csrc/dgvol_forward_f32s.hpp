@@ -380,7 +380,6 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
   using Sh = Shape<NP>;
   static_assert(WPB >= Sh::NCHUNK, "one wave per output chunk");
   constexpr int KS = Sh::KS16;
-  constexpr int LD = chunk_ld<NP, 4>();
   constexpr int TPW = chunk_tpw<NP, 4>();
   constexpr int OLD = chunk_old<NP, 4>();
   constexpr int OSUP = TPW * 16 * OLD;
@@ -403,8 +402,28 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
       }
     }
   }
-  auto chunk = [&](const float* us, float* ostg, const float* gs, uint32_t col0, uint32_t k_lo) {
+  // u is staged split: BF16 hi and lo planes, row stride LDB; the entries past
+  // Np of every row are zeroed here once (staging never writes them)
+  constexpr int LDB = chunk_ldb<NP>();
+  constexpr int PLANE = TPW * 16 * LDB;  // elements of one plane
+  {
+    uint16_t* h = reinterpret_cast<uint16_t*>(lds);
+    for (int x = threadIdx.x; x < TPW * 16 * (LDB - NP); x += WAVE * WPB) {
+      const int c = x / (LDB - NP), j = NP + x % (LDB - NP);
+      h[c * LDB + j] = 0;
+      h[PLANE + c * LDB + j] = 0;
+    }
+  }
+  auto put_u = [](char* us, int c, int i, float x) {
+    uint16_t* h = reinterpret_cast<uint16_t*>(us);
+    Bf16x8Bits hb, lb;
+    split_bf16_pair(x, 0.0f, hb, lb, 0);
+    h[c * LDB + i] = hb.v[0];
+    h[PLANE + c * LDB + i] = lb.v[0];
+  };
+  auto chunk = [&](const char* usb, float* ostg, const float* gs, uint32_t col0, uint32_t k_lo) {
     if (!mma) return;
+    const uint16_t* uh = reinterpret_cast<const uint16_t*>(usb);
 #pragma unroll
     for (int tp = 0; tp < TPW; ++tp) {
       const int cl = tp * 16 + n;
@@ -413,15 +432,8 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
       for (int tt = 0; tt < 3; ++tt) acc[tt] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
       for (int s = 0; s < KS; ++s) {
-        Bf16x8Bits bh, bl;
-        const f32x4* bp = reinterpret_cast<const f32x4*>(us + cl * LD + 32 * s + 8 * g);
-        const f32x4 v0 = bp[0], v1 = bp[1];
-#pragma unroll
-        for (int e = 0; e < 8; e += 2) {
-          const int j = 32 * s + 8 * g + e;
-          const float x0 = e < 4 ? v0[e] : v1[e - 4], x1 = e < 4 ? v0[e + 1] : v1[e - 3];
-          split_bf16_pair(j < NP ? x0 : 0.0f, j + 1 < NP ? x1 : 0.0f, bh, bl, e);
-        }
+        const Bf16x8Bits bh = *reinterpret_cast<const Bf16x8Bits*>(uh + cl * LDB + 32 * s + 8 * g);
+        const Bf16x8Bits bl = *reinterpret_cast<const Bf16x8Bits*>(uh + PLANE + cl * LDB + 32 * s + 8 * g);
 #pragma unroll
         for (int tt = 0; tt < 3; ++tt) {
           acc[tt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(as_bf16x8(al[tt][s]), as_bf16x8(bh), acc[tt], 0, 0, 0);
@@ -446,7 +458,7 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
       }
     }
   };
-  chunkreg_loop<float, NP, WPB, KS>(p, bid, nblk, lds, chunk);
+  chunkreg_loop<float, NP, WPB, KS>(p, bid, nblk, lds, chunk, put_u);
 }
 
 }  // namespace dgvol
