@@ -484,13 +484,14 @@ constexpr int fwd_f64_chunkreg_lds() { return chunk_lds<NP, 8>(); }
 // loads and stores go through buffer ranges (no branches around them), so the
 // compiler's waits count exactly the operations in flight; with conditional
 // loads and stores every wait had become a wait for everything, including the
-// previous iteration's stores (order 7 took 13 % longer).
+// previous iteration's stores (order 7 took 13 % longer).  The body lays out
+// the staged u: put_u(us, column, node, value) stores one word of it (FP64:
+// padded rows; split-BF16: the value split into BF16 hi and lo planes).
 template <typename T, int NP, int WPB, int KS, int VEC, typename ChunkFn, typename PutU>
 __device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t bid, uint32_t nblk, char* lds,
                                                   ChunkFn&& chunk, PutU&& put_u) {
   constexpr int WORD = sizeof(T);
   constexpr int TPW = chunk_tpw<NP, WORD>();
-  constexpr int LD = chunk_ld<NP, WORD>();
   constexpr int SUP = TPW * 16 * NP;        // words of one plane of the super-tile
   constexpr int OLD = chunk_old<NP, WORD>();
   constexpr int OSUP = TPW * 16 * OLD;      // words of one plane of the output tile
@@ -499,7 +500,6 @@ __device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t 
   constexpr int NLD = (SUP / VEC + NT - 1) / NT;  // u vectors loaded per thread per iteration
   constexpr int GMAX = TPW * 16 * 9;        // geometric-factor words of at most TPW*16 elements
   constexpr int NG = (GMAX + NT - 1) / NT;  // G words loaded per thread per iteration
-  (void)LD;
   char* us = lds;  // laid out by put_u (the body's staging of one u word)
   T* ostg = reinterpret_cast<T*>(lds + align16(chunk_us_bytes<NP, WORD>()));
   T* gs = reinterpret_cast<T*>(lds + align16(chunk_us_bytes<NP, WORD>()) + align16(3 * OSUP * WORD));
