@@ -420,6 +420,29 @@ def test_f32s_orders(N):
     _check_f32s(D, G, u, got)
 
 
+@pytest.mark.parametrize("N,shift", [(4, 0), (7, 0), (7, 1)])
+def test_f32s_guard_bands(N, shift):
+    """Split-BF16 writes stay inside out (order 7 stores through buffer ranges);
+    shift = 1 moves out off 8-byte alignment (the single-float path); repeated
+    launches give bitwise identical results."""
+    K, F = 301, 3
+    Np = oracle.num_nodes(N)
+    _say(f"f32s guards N={N} K={K} F={F} shift={shift}")
+    D, G, u = make_case(N, K, F, 910 + N, "normal")
+    D32, G32, u32 = (dev(x.astype(np.float32)) for x in (D, G, u))
+    n = 3 * K * F * Np
+    guard = 2048 + shift
+    buf = torch.full((n + 2 * guard,), 1.5e30, dtype=torch.float32, device="cuda")
+    out = buf[guard:guard + n].view(3, K, F, Np)
+    dgvol.dg_volume_f32s(D32, G32, u32, out=out)
+    b = host(buf)
+    assert (b[:guard] == np.float32(1.5e30)).all() and (b[guard + n:] == np.float32(1.5e30)).all()
+    first = host(out).copy()
+    _check_f32s(D, G, u, first.astype(np.float64))
+    again = host(dgvol.dg_volume_f32s(D32, G32, u32))
+    assert np.array_equal(again, first)
+
+
 # ------------------------------------------------------------------ bandwidth calibration kernel
 
 def test_stream_calibrate():
