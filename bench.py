@@ -427,6 +427,24 @@ def main():
             "adjoint_hbm_frac": round(K5 * adj_bytes_per_element(F5, Np5) / (ka * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del D5, G5, u5, o5, g5, gu5, gG5, gD5, wk5
         torch.cuda.empty_cache()
+        # adjoint at the orders whose D does not fit LDS (two chunk-register passes)
+        for Nh, Kh in ((6, 1 << 17), (7, 1 << 16)):
+            Nph = setup_host.NODE_COUNTS[Nh]
+            Dh = torch.from_numpy(setup_host.reference_matrices(Nh)).to(dev)
+            Gh = torch.from_numpy(setup_host.geometric_factors(synth.tet_vertices(Kh, synth.mesh_seed(5) + Nh))).to(dev)
+            uh = torch.from_numpy(synth.fields(Kh, F5, Nph, synth.field_seed(5) + Nh, "uniform")).to(dev)
+            gh = torch.from_numpy(synth.fields(Kh, F5, Nph, synth.field_seed(5) + 10 * Nh, "normal")).to(dev)
+            gh = torch.stack([gh, 0.5 * gh, -gh])
+            guh, gGh = torch.empty_like(uh), torch.empty_like(Gh)
+            _, perh = time_launches(lambda: dgvol.dg_volume_adjoint(Dh, Gh, uh, gh, gu=guh, gG=gGh), 20, 3, torch,
+                                    min_warm_ms=WARM_MS)
+            kh = float(np.mean(perh))
+            flh = Kh * adj_flops_per_element(F5, Nph)
+            forms[f"fp64_adjoint_order{Nh}_K{Kh}_F{F5}"] = {
+                "adjoint_GDOF/s": round(Kh * F5 * Nph / (kh * 1e-3) / 1e9, 3), "adjoint_call_ms": round(kh, 5),
+                "adjoint_fp64_frac": round(flh / (kh * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)}
+            del Dh, Gh, uh, gh, guh, gGh
+            torch.cuda.empty_cache()
         forms["mixed_orders1to7_F3"] = mixed_orders(torch, dev)
         rec["forms"] = forms
 
