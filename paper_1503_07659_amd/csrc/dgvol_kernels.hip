@@ -250,8 +250,9 @@ static dg_status launch_gd_f64(const double* G, const double* u, const double* g
 // Estimate of one 16-column tile (seconds), used to split workgroups between
 // groups when the caller gives no measured cost: the spec roofline time
 // (8 TB/s, spec matrix peak) divided by the fraction of it that the order's
-// default body reached in single-order launches on MI355X (large K, F = 3).
-// Only the ratios between groups matter.
+// default body reached in single-order launches on MI355X (F = 3, at the
+// autotuner's problem size: at least 2^15 tiles and 256 MB).  Only the ratios
+// between groups matter.
 static double tile_cost_estimate(int form, int Np, uint32_t F) {
   const double word = form == DG_FORM_F64 ? 8.0 : 4.0;
   const double bytes = 16.0 * word * (4.0 * Np + 9.0 / F);
@@ -260,13 +261,13 @@ static double tile_cost_estimate(int form, int Np, uint32_t F) {
   const double peak = form == DG_FORM_F64 ? 78.6e12 : 2.5e15 / 3.0;  // three BF16 passes
   double eff;
   switch (Np) {
-    case 4: eff = form == DG_FORM_F64 ? 0.70 : 0.52; break;
-    case 10: eff = form == DG_FORM_F64 ? 0.70 : 0.68; break;
-    case 20: eff = form == DG_FORM_F64 ? 0.73 : 0.68; break;
-    case 35: eff = form == DG_FORM_F64 ? 0.58 : 0.68; break;
-    case 56: eff = form == DG_FORM_F64 ? 0.63 : 0.78; break;
-    case 84: eff = form == DG_FORM_F64 ? 0.46 : 0.68; break;
-    default: eff = form == DG_FORM_F64 ? 0.67 : 0.50; break;  // Np = 120
+    case 4: eff = form == DG_FORM_F64 ? 0.71 : 0.49; break;
+    case 10: eff = form == DG_FORM_F64 ? 0.65 : 0.65; break;
+    case 20: eff = form == DG_FORM_F64 ? 0.67 : 0.60; break;
+    case 35: eff = form == DG_FORM_F64 ? 0.60 : 0.55; break;
+    case 56: eff = form == DG_FORM_F64 ? 0.58 : 0.76; break;
+    case 84: eff = form == DG_FORM_F64 ? 0.43 : 0.70; break;
+    default: eff = form == DG_FORM_F64 ? 0.60 : 0.55; break;  // Np = 120
   }
   return std::max(bytes / bw, flops / peak) / eff;
 }
