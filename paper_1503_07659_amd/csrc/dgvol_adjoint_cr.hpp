@@ -15,9 +15,10 @@
 //     column, so it needs one element's geometric factors) into LDS, each wave
 //     runs its k-steps, and gu leaves through an LDS tile as contiguous runs.
 //   pass B (gG):  gG[k][3a+b] = sum_f sum_i gout_b[c][i] (D_a u)[c][i].
-//     Wave w < NCHUNK keeps the A operands of forward output chunk w (as the
-//     forward chunk-register body), recomputes D u for its 4 node triples from
-//     u staged in LDS, and reduces it with gout at its lanes' nodes.  Tiles are
+//     Wave w < NCH keeps the A operands of output chunk w (3 tiles, as the
+//     forward chunk-register body, or 2 at Np = 84 so that all 8 waves work),
+//     recomputes D u for the chunk's slots from u staged in LDS, and reduces
+//     it with gout at its lanes' nodes (at most 4 node triples).  Tiles are
 //     whole elements (16/F of them, or one element in ceil(F/16) sub-tiles when
 //     F > 16) so every element's sums finish inside one workgroup; the partial
 //     sums are added in a fixed order (lane groups, then sub-tiles, then
@@ -26,6 +27,8 @@
 // gout is read twice (once per pass), u once; the matrix work equals the
 // single-pass adjoint's.
 #pragma once
+
+#include <type_traits>
 
 #include "dgvol_device.hpp"
 #include "dgvol_layout.hpp"
@@ -150,7 +153,15 @@ struct AdjCrB {
   static constexpr int KS = Shape<NP>::KS64;
   static constexpr int LD = NP + 1;                    // odd row stride of the u stage
   static constexpr int NLD = (16 * NP + NTH - 1) / NTH;
-  static_assert(Shape<NP>::NCHUNK <= ADJCR_WPB, "one wave per output chunk");
+  // Tiles per output chunk: 3 (4 whole node triples per lane), but 2 at
+  // Np = 84, whose 16 tiles then give all 8 waves two; with 3-tile chunks two
+  // waves sat idle and one SIMD carried two full chunks.  The pass only sums
+  // gout * (D u) over nodes, so a chunk need not hold whole triples.
+  static constexpr int TPC = NP == 84 ? 2 : 3;
+  static constexpr int NCH = (Shape<NP>::MT + TPC - 1) / TPC;  // chunks (waves with work)
+  static constexpr int SPC = 4 * TPC;                         // slots per chunk
+  static constexpr int NTRI = SPC % 3 == 0 ? SPC / 3 : (SPC + 4) / 3;  // node triples a chunk touches
+  static_assert(NCH <= ADJCR_WPB, "one wave per output chunk");
 };
 
 template <int NP>
@@ -168,12 +179,14 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
   const int lane = tid & 63;
   const int n = lane & 15, g = lane >> 4;
   const int w = tid >> 6;
-  const bool mma = w < Sh::NCHUNK;
+  const bool mma = w < S::NCH;
   const int ch = mma ? w : 0;
-  double areg[3][S::KS];
+  const int tau0 = S::SPC * ch / 3;  // first node triple of the chunk
+  const int r0 = S::SPC * ch % 3;    // its first slot's direction
+  double areg[S::TPC][S::KS];
 #pragma unroll
-  for (int tt = 0; tt < 3; ++tt) {
-    const int T = 3 * ch + tt;
+  for (int tt = 0; tt < S::TPC; ++tt) {
+    const int T = S::TPC * ch + tt;
 #pragma unroll
     for (int s = 0; s < S::KS; ++s) areg[tt][s] = (mma && T < Sh::MT) ? afrag_f64<NP>(D, T, s, lane) : 0.0;
   }
@@ -215,21 +228,21 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
       // addresses: unconditional loads; entries outside are zeroed)
       const bool valid = (uint32_t)n < nc;
       const int64_t cb = (int64_t)(c0 + (valid ? n : 0)) * NP;
-      double go[4][3];
+      double go[S::NTRI][3];
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        const int i = 4 * (4 * ch + x) + g;
+      for (int x = 0; x < S::NTRI; ++x) {
+        const int i = 4 * (tau0 + x) + g;
         const int ic = min(i, NP - 1);
-        const bool ok = valid && 4 * ch + x < Sh::TRIP && i < NP;
+        const bool ok = valid && tau0 + x < Sh::TRIP && i < NP;
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb) {
           const double v = gout[bb * plane + cb + ic];
           go[x][bb] = ok ? v : 0.0;
         }
       }
-      f64x4 acc[3];
+      f64x4 acc[S::TPC];
 #pragma unroll
-      for (int tt = 0; tt < 3; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
+      for (int tt = 0; tt < S::TPC; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
       auto bval = [&](int s) __attribute__((always_inline)) {
         const int j = 4 * s + g;
         const double v = us[n * S::LD + min(j, NP - 1)];
@@ -240,7 +253,7 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
       for (int s = 0; s < S::KS; ++s) {
         const double bnxt = s + 1 < S::KS ? bval(s + 1) : 0.0;
 #pragma unroll
-        for (int tt = 0; tt < 3; ++tt)
+        for (int tt = 0; tt < S::TPC; ++tt)
           acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[tt][s], bcur, acc[tt], 0, 0, 0);
         bcur = bnxt;
       }
@@ -248,19 +261,27 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
       double P[9];
 #pragma unroll
       for (int c = 0; c < 9; ++c) P[c] = 0.0;
+      // slot l of the chunk: direction (r0 + l) % 3 of its triple (r0 + l) / 3,
+      // with r0 (wave-uniform) made a compile-time constant per branch
+      auto accumulate = [&](auto R0) __attribute__((always_inline)) {
+        constexpr int rr = decltype(R0)::value;
 #pragma unroll
-      for (int x = 0; x < 4; ++x) {
-        if (4 * ch + x < Sh::TRIP) {
-#pragma unroll
-          for (int a = 0; a < 3; ++a) {
-            const int l = 3 * x + a;
+        for (int l = 0; l < S::SPC; ++l) {
+          const int a = (rr + l) % 3, x = (rr + l) / 3;
+          if (S::SPC * ch + l < Sh::SLOTS) {
             const double R = acc[l >> 2][l & 3];
             P[3 * a] += go[x][0] * R;
             P[3 * a + 1] += go[x][1] * R;
             P[3 * a + 2] += go[x][2] * R;
           }
         }
-      }
+      };
+      if (S::SPC % 3 == 0 || r0 == 0)  // 3-tile chunks start on a whole triple
+        accumulate(std::integral_constant<int, 0>{});
+      else if (r0 == 1)
+        accumulate(std::integral_constant<int, 1>{});
+      else
+        accumulate(std::integral_constant<int, 2>{});
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
         P[c] += __shfl_xor(P[c], 16);
@@ -283,7 +304,7 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
         double s = 0.0;
         for (int m = lo; m < hi; ++m) {
           double sw = 0.0;
-          for (int ww = 0; ww < Sh::NCHUNK; ++ww) sw += red[ww][m][c];
+          for (int ww = 0; ww < S::NCH; ++ww) sw += red[ww][m][c];
           s += sw;
         }
         gG[(int64_t)(t * E + e) * 9 + c] = s;
