@@ -71,22 +71,23 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
   // staging: thread (cc, rr) owns column cc of the tile and nodes rr + TPC x
   const int cc = tid / S::TPC, rr = tid % S::TPC;
   double r0[S::NX], r1[S::NX], r2[S::NX], rG[9];
-  // Loads from clamped addresses (a tile past the end reads the last column;
-  // its values are not used), so they are unconditional and the compiler's
-  // waits count exactly the memory operations in flight.
+  // Loads are unconditional, so the compiler's waits count exactly the
+  // memory operations in flight: gout moves through one buffer range per
+  // plane over the tile's columns (zero past it, and for padding nodes), G
+  // from a clamped column (a tile past the end rereads the last one).
   auto load = [&](uint32_t t) __attribute__((always_inline)) {
     const uint32_t col = min(t * 16 + cc, ncols - 1);
-    const bool v = t * 16 + cc < ncols;
-    const int64_t base = (int64_t)col * NP;
+    const uint32_t gbytes = min(16u, ncols - t * 16) * NP * 8u;
+    __amdgpu_buffer_rsrc_t rgo[3];
+#pragma unroll
+    for (int b = 0; b < 3; ++b) rgo[b] = buffer_range(gout + b * plane + (int64_t)t * 16 * NP, gbytes);
 #pragma unroll
     for (int x = 0; x < S::NX; ++x) {
       const int i = rr + S::TPC * x;
-      const int ic = min(i, NP - 1);
-      const bool ok = v && i < NP;
-      const double g0 = gout[base + ic], g1 = gout[plane + base + ic], g2 = gout[2 * plane + base + ic];
-      r0[x] = ok ? g0 : 0.0;
-      r1[x] = ok ? g1 : 0.0;
-      r2[x] = ok ? g2 : 0.0;
+      const uint32_t off = i < NP ? (uint32_t)(cc * NP + i) * 8u : gbytes;
+      r0[x] = buffer_load_f64(rgo[0], off);
+      r1[x] = buffer_load_f64(rgo[1], off);
+      r2[x] = buffer_load_f64(rgo[2], off);
     }
     const int64_t gb = (int64_t)(col / F) * 9;
 #pragma unroll
@@ -196,19 +197,19 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
     return F <= 16 ? ne * F : F;
   };
   double ur[S::NLD];
+  // u and gout move through buffer ranges (32-bit offsets, zero past the
+  // range, empty past the last tile), which frees the address registers of
+  // the clamped 64-bit form
   auto load = [&](uint32_t tt, uint32_t sub) __attribute__((always_inline)) {
-    const uint32_t c0 = tt * E * F + 16 * sub;
-    const int cnt = (int)min(16u, tile_cols(tt) - 16 * sub) * NP;
-    const double* __restrict__ src = u + (int64_t)c0 * NP;
+    const bool any = tt < ntiles;
+    const uint32_t c0 = any ? tt * E * F + 16 * sub : 0u;
+    const uint32_t cnt = any ? min(16u, tile_cols(tt) - 16 * sub) * NP : 0u;
+    const __amdgpu_buffer_rsrc_t ru = buffer_range(u + (int64_t)c0 * NP, cnt * 8u);
 #pragma unroll
-    for (int q = 0; q < S::NLD; ++q) {
-      const int x = tid + S::NTH * q;
-      const double v = src[min(x, cnt - 1)];
-      ur[q] = x < cnt ? v : 0.0;
-    }
+    for (int q = 0; q < S::NLD; ++q) ur[q] = buffer_load_f64(ru, (uint32_t)(tid + S::NTH * q) * 8u);
   };
   uint32_t t = blockIdx.x, sub = 0;
-  if (t < ntiles) load(t, 0);
+  load(t, 0);
   while (t < ntiles) {
     const uint32_t ncolt = tile_cols(t);
     const uint32_t c0 = t * E * F + 16 * sub;
@@ -222,23 +223,22 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
     const bool last = sub + 1 == nsub;
     const uint32_t t_next = last ? t + gridDim.x : t;
     const uint32_t sub_next = last ? 0u : sub + 1;
-    if (t_next < ntiles) load(t_next, sub_next);
+    load(t_next, sub_next);
     if (mma) {
       // this lane's gout values, requested before the products (clamped
       // addresses: unconditional loads; entries outside are zeroed)
-      const bool valid = (uint32_t)n < nc;
-      const int64_t cb = (int64_t)(c0 + (valid ? n : 0)) * NP;
+      const uint32_t gbytes = nc * NP * 8u;
+      __amdgpu_buffer_rsrc_t rgo[3];
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb) rgo[bb] = buffer_range(gout + bb * plane + (int64_t)c0 * NP, gbytes);
       double go[S::NTRI][3];
 #pragma unroll
       for (int x = 0; x < S::NTRI; ++x) {
         const int i = 4 * (tau0 + x) + g;
-        const int ic = min(i, NP - 1);
-        const bool ok = valid && tau0 + x < Sh::TRIP && i < NP;
+        // padding nodes read from the range's end, which loads zero
+        const uint32_t off = (tau0 + x < Sh::TRIP && i < NP) ? (uint32_t)(n * NP + i) * 8u : gbytes;
 #pragma unroll
-        for (int bb = 0; bb < 3; ++bb) {
-          const double v = gout[bb * plane + cb + ic];
-          go[x][bb] = ok ? v : 0.0;
-        }
+        for (int bb = 0; bb < 3; ++bb) go[x][bb] = buffer_load_f64(rgo[bb], off);
       }
       f64x4 acc[S::TPC];
 #pragma unroll
