@@ -10,7 +10,9 @@
 //                 W_a[c][i] = sum_b G[k][3a+b] gout_b[c][i]   (k = c / F).
 //     Wave w < ceil(Np/16) owns output rows j = 16w..16w+15 and keeps the A
 //     operands of the transposed product (k = slot sp: direction sp % 3,
-//     nodes 4 (sp/3) + lane group) for all 3 ceil(Np/4) k-steps.  Per 16
+//     nodes 4 (sp/3) + lane group) for all 3 ceil(Np/4) k-steps (at Np = 84,
+//     whose 6 tiles leave two waves spare, the spare waves take the last
+//     k-steps of three tiles each).  Per 16
 //     columns the workgroup forms W from gout and G (each thread stages a fixed
 //     column, so it needs one element's geometric factors) into LDS, each wave
 //     runs its k-steps, and gu leaves through an LDS tile as contiguous runs.
@@ -48,6 +50,14 @@ struct AdjCrA {
   static constexpr int TPC = NTH / 16;                // threads staging one column
   static constexpr int NX = (NP + TPC - 1) / TPC;     // nodes per thread
   static_assert(MTJ <= ADJCR_WPB, "one wave per output tile");
+  // Np = 84 has 6 output tiles for 8 waves.  There each owner wave runs the
+  // first KA k-steps of its tile, and the two spare waves run the last KB
+  // k-steps of three tiles each into a second partial, so every SIMD carries
+  // about the same number of products.
+  static constexpr bool SPLIT = MTJ == 6 && ADJCR_WPB == 8;
+  static constexpr int KA = SPLIT ? 48 : KT;
+  static constexpr int KB = KT - KA;
+  static_assert(!SPLIT || 3 * KB <= KA, "a helper wave's operands fit the owner's array");
 };
 
 template <int NP>
@@ -59,14 +69,24 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
   using S = AdjCrA<NP>;
   __shared__ double ws[16 * S::LDW];  // W[c][a Np + i]
   __shared__ double ostg[16 * NP];    // gu tile, column-major runs
+  __shared__ double ostg2[S::SPLIT ? 16 * NP : 1];  // the helper waves' partial
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int n = lane & 15, g = lane >> 4;
   const int w = tid >> 6;
   const bool mma = w < S::MTJ;
-  double areg[S::KT];
+  const bool helper = S::SPLIT && !mma;
+  const int hw = helper ? w - S::MTJ : 0;  // helper index: tiles 3 hw .. 3 hw + 2
+  double areg[S::KA];
 #pragma unroll
-  for (int sp = 0; sp < S::KT; ++sp) areg[sp] = mma ? afragT_f64<NP>(D, w, sp, lane) : 0.0;
+  for (int sp = 0; sp < S::KA; ++sp) {
+    double a = 0.0;
+    if (mma)
+      a = afragT_f64<NP>(D, w, sp, lane);
+    else if (helper && sp < 3 * S::KB)
+      a = afragT_f64<NP>(D, 3 * hw + sp / S::KB, S::KA + sp % S::KB, lane);
+    areg[sp] = a;
+  }
 
   // staging: thread (cc, rr) owns column cc of the tile and nodes rr + TPC x
   const int cc = tid / S::TPC, rr = tid % S::TPC;
@@ -124,8 +144,8 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
       };
       double bcur = bval(0);
 #pragma unroll
-      for (int sp = 0; sp < S::KT; ++sp) {
-        const double bnxt = sp + 1 < S::KT ? bval(sp + 1) : 0.0;
+      for (int sp = 0; sp < S::KA; ++sp) {
+        const double bnxt = sp + 1 < S::KA ? bval(sp + 1) : 0.0;
         acc = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[sp], bcur, acc, 0, 0, 0);
         bcur = bnxt;
       }
@@ -135,12 +155,45 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
         if (j < NP) ostg[n * NP + j] = acc[q];
       }
     }
+    if constexpr (S::SPLIT) {
+      if (helper) {
+        f64x4 acc[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) acc[r] = f64x4{0.0, 0.0, 0.0, 0.0};
+        auto bval = [&](int sp) __attribute__((always_inline)) {
+          const int i = 4 * (sp / 3) + g;
+          const double v = ws[n * S::LDW + (sp % 3) * NP + min(i, NP - 1)];
+          return i < NP ? v : 0.0;
+        };
+        double bcur = bval(S::KA);
+#pragma unroll
+        for (int s2 = 0; s2 < S::KB; ++s2) {
+          const double bnxt = s2 + 1 < S::KB ? bval(S::KA + s2 + 1) : 0.0;
+#pragma unroll
+          for (int r = 0; r < 3; ++r)
+            acc[r] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[r * S::KB + s2], bcur, acc[r], 0, 0, 0);
+          bcur = bnxt;
+        }
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int j = 16 * (3 * hw + r) + 4 * q + g;
+            if (j < NP) ostg2[n * NP + j] = acc[r][q];
+          }
+        }
+      }
+    }
     __syncthreads();
     const __amdgpu_buffer_rsrc_t ro = buffer_range(gu + (int64_t)col0 * NP, (uint32_t)cnt * 8u);
 #pragma unroll
     for (int q = 0; q < NST; ++q) {
       const int x = tid + S::NTH * q;
-      buffer_store_f64(ro, (uint32_t)x * 8u, ostg[min(x, 16 * NP - 1)]);
+      const int xc = min(x, 16 * NP - 1);
+      if constexpr (S::SPLIT)
+        buffer_store_f64(ro, (uint32_t)x * 8u, ostg[xc] + ostg2[xc]);
+      else
+        buffer_store_f64(ro, (uint32_t)x * 8u, ostg[xc]);
     }
     stage();
   }
