@@ -57,6 +57,9 @@ struct AdjCrA {
   static constexpr bool SPLIT = MTJ == 6 && ADJCR_WPB == 8;
   static constexpr int KA = SPLIT ? 48 : KT;
   static constexpr int KB = KT - KA;
+  // at Np = 120 the last KL k-steps' operands wait in LDS, not registers
+  static constexpr int KL = NP == 120 ? 12 : 0;
+  static constexpr int KR = KA - KL;
   static_assert(!SPLIT || 3 * KB <= KA, "a helper wave's operands fit the owner's array");
 };
 
@@ -70,6 +73,7 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
   __shared__ double ws[16 * S::LDW];  // W[c][a Np + i]
   __shared__ double ostg[16 * NP];    // gu tile, column-major runs
   __shared__ double ostg2[S::SPLIT ? 16 * NP : 1];  // the helper waves' partial
+  __shared__ double atl[S::KL ? ADJCR_WPB * S::KL * WAVE : 1];  // operand tail, per wave and lane
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int n = lane & 15, g = lane >> 4;
@@ -85,7 +89,10 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
       a = afragT_f64<NP>(D, w, sp, lane);
     else if (helper && sp < 3 * S::KB)
       a = afragT_f64<NP>(D, 3 * hw + sp / S::KB, S::KA + sp % S::KB, lane);
-    areg[sp] = a;
+    if (sp < S::KR)
+      areg[sp] = a;
+    else
+      atl[(w * S::KL + sp - S::KR) * WAVE + lane] = a;  // read back by this lane only
   }
 
   // staging: thread (cc, rr) owns column cc of the tile and nodes rr + TPC x
@@ -146,7 +153,8 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
 #pragma unroll
       for (int sp = 0; sp < S::KA; ++sp) {
         const double bnxt = sp + 1 < S::KA ? bval(sp + 1) : 0.0;
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[sp], bcur, acc, 0, 0, 0);
+        const double a = sp < S::KR ? areg[sp] : atl[(w * S::KL + sp - S::KR) * WAVE + lane];
+        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bcur, acc, 0, 0, 0);
         bcur = bnxt;
       }
 #pragma unroll
@@ -216,6 +224,9 @@ struct AdjCrB {
   static constexpr int SPC = 4 * TPC;                         // slots per chunk
   static constexpr int NTRI = SPC % 3 == 0 ? SPC / 3 : (SPC + 4) / 3;  // node triples a chunk touches
   static_assert(NCH <= ADJCR_WPB, "one wave per output chunk");
+  // at Np = 120 the last tile's last KL k-steps' operands wait in LDS
+  static constexpr int KL = NP == 120 ? 8 : 0;
+  static constexpr int KR = KS - KL;
 };
 
 template <int NP>
@@ -237,12 +248,19 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
   const int ch = mma ? w : 0;
   const int tau0 = S::SPC * ch / 3;  // first node triple of the chunk
   const int r0 = S::SPC * ch % 3;    // its first slot's direction
+  __shared__ double atl[S::KL ? ADJCR_WPB * S::KL * WAVE : 1];  // operand tail, per wave and lane
   double areg[S::TPC][S::KS];
 #pragma unroll
   for (int tt = 0; tt < S::TPC; ++tt) {
     const int T = S::TPC * ch + tt;
 #pragma unroll
-    for (int s = 0; s < S::KS; ++s) areg[tt][s] = (mma && T < Sh::MT) ? afrag_f64<NP>(D, T, s, lane) : 0.0;
+    for (int s = 0; s < S::KS; ++s) {
+      const double a = (mma && T < Sh::MT) ? afrag_f64<NP>(D, T, s, lane) : 0.0;
+      if (tt < S::TPC - 1 || s < S::KR)
+        areg[tt][s] = a;
+      else
+        atl[(w * S::KL + s - S::KR) * WAVE + lane] = a;  // read back by this lane only
+    }
   }
   // columns of tile t (whole elements) and of its sub-tile `sub`
   auto tile_cols = [&](uint32_t tt) __attribute__((always_inline)) {
@@ -306,8 +324,11 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
       for (int s = 0; s < S::KS; ++s) {
         const double bnxt = s + 1 < S::KS ? bval(s + 1) : 0.0;
 #pragma unroll
-        for (int tt = 0; tt < S::TPC; ++tt)
-          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[tt][s], bcur, acc[tt], 0, 0, 0);
+        for (int tt = 0; tt < S::TPC; ++tt) {
+          const double a =
+              (tt < S::TPC - 1 || s < S::KR) ? areg[tt][s] : atl[(w * S::KL + s - S::KR) * WAVE + lane];
+          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bcur, acc[tt], 0, 0, 0);
+        }
         bcur = bnxt;
       }
       // P[3a+b] = sum over this lane's nodes of gout_b * (D_a u)
