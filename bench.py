@@ -127,18 +127,34 @@ def time_launches(fn, steps, warmup, torch, min_warm_ms=0.0):
     return evs[0].elapsed_time(evs[-1]) / steps, per
 
 
-def cpu_baseline(D, G, u, min_seconds=10.0, max_reps=1000):
-    """The FP64 oracle on the host cores, on the first elements of the same workload."""
+def cpu_baseline(D, G, u, min_seconds=10.0, max_reps=1000, samples=None):
+    """The FP64 oracle on the host cores, on the first elements of the same workload.
+
+    `samples`: optional {name: (gpu output of these elements, "f64" | "f32s")}; each is
+    compared with the oracle's output of the timed passes (accuracy of the timed GPU
+    outputs on the sampled elements), returned under "accuracy_vs_oracle"."""
     import oracle
     K, F, Np = u.shape
     oracle.volume(D, G[:64], u[:64])  # load/compile outside the timing
     reps, t0 = 0, time.perf_counter()
     while True:
-        oracle.volume(D, G, u)
+        ref = oracle.volume(D, G, u)
         reps += 1
         el = time.perf_counter() - t0
         if el >= min_seconds or reps >= max_reps:
             break
+    acc = {}
+    if samples:
+        cond = oracle.volume(np.abs(D), np.abs(G), np.abs(u))
+        for name, got in samples.items():
+            got = np.asarray(got, dtype=np.float64)
+            planes = []
+            for b in range(3):
+                e = np.abs(got[b] - ref[b])
+                planes.append({"max_rel": float(e.max() / np.abs(ref[b]).max()),
+                               "rms_rel": float(np.linalg.norm(e) / np.linalg.norm(ref[b])),
+                               "max_err_over_cond": float((e / np.maximum(cond[b], 1e-300)).max())})
+            acc[name] = planes
     cpu = "unknown"
     try:
         with open("/proc/cpuinfo") as fh:
@@ -148,9 +164,44 @@ def cpu_baseline(D, G, u, min_seconds=10.0, max_reps=1000):
                     break
     except OSError:
         pass
-    return {"value": round(reps * K * F * Np / el / 1e9, 4), "unit": "GDOF/s",
-            "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu,
-            "sample": f"first {K} of {WORKLOAD['K']} elements (order 4, F=5), {reps} pass(es) in {el:.1f} s"}
+    res = {"value": round(reps * K * F * Np / el / 1e9, 4), "unit": "GDOF/s",
+           "cores": oracle.num_threads(), "kind": "oracle", "cpu_model": cpu,
+           "sample": f"first {K} of {WORKLOAD['K']} elements (order 4, F=5), {reps} pass(es) in {el:.1f} s"}
+    if acc:
+        res["accuracy_vs_oracle"] = acc
+    return res
+
+
+def split_errors_gpu(got, ref, torch):
+    """Per output plane: max|e|/max|ref| and ||e||_2/||ref||_2 of got against ref (GPU tensors)."""
+    res = []
+    for b in range(ref.shape[0]):
+        e = got[b].double() - ref[b]
+        res.append({"max_rel": float(e.abs().max() / ref[b].abs().max()),
+                    "rms_rel": float(torch.linalg.vector_norm(e) / torch.linalg.vector_norm(ref[b]))})
+    return res
+
+
+def git_revision():
+    """HEAD of the source tree, if it is a git checkout (copies without .git report None)."""
+    import subprocess
+    try:
+        r = subprocess.run(["git", "-C", ROOT, "rev-parse", "HEAD"], capture_output=True, text=True, timeout=10)
+        return r.stdout.strip() or None if r.returncode == 0 else None
+    except (OSError, subprocess.SubprocessError):
+        return None
+
+
+def source_sha():
+    """SHA-256 over every library source, the header and this file (identifies the code timed)."""
+    h = hashlib.sha256()
+    files = sorted(glob.glob(os.path.join(KERNEL_SRC_DIR, "*"))) + [os.path.join(ROOT, "include", "dgvol.h"),
+                                                                    os.path.abspath(__file__)]
+    for f in files:
+        h.update(os.path.basename(f).encode())
+        with open(f, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 def mixed_orders(torch, dev):
@@ -176,8 +227,10 @@ def mixed_orders(torch, dev):
         outs = [torch.empty((3,) + tuple(t[2].shape), dtype=dt, device=dev) for t in trip]
         ms_auto, _ = time_launches(lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs), 20, 3, torch,
                                    min_warm_ms=WARM_MS)
-        bodies, costs = autotune.plan(trip, form)
-        tuned = lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs, bodies=bodies, costs=costs)  # noqa: E731
+        # tuning (untimed): every variant of every order, then whole candidate plans on these groups
+        variants, costs, cand = autotune.plan_batch(trip, form, outs=outs)
+        tuned = lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs, variants=variants,  # noqa: E731
+                                                costs=costs)
         ms_tuned, _ = time_launches(tuned, 20, 3, torch, min_warm_ms=WARM_MS)
         cap = CapturedLaunch(tuned)
         ms_graph, _ = time_launches(cap.replay, 20, 3, torch, min_warm_ms=WARM_MS)
@@ -194,7 +247,10 @@ def mixed_orders(torch, dev):
                      "tuned_ms": round(ms_tuned, 5), "default_ms": round(ms_auto, 5),
                      "one_launch_per_order_ms": round(ms_sep, 5), "roofline_ms": round(roof * 1e3, 5),
                      "frac_of_roofline": round(roof * 1e3 / ms_graph, 4),
-                     "bodies": {str(N): int(b) for N, b in zip(sizes, bodies)}}
+                     "variants": {str(N): dict(dgvol.variant_info(form, setup_host.NODE_COUNTS[N],
+                                                                  v if v >= 0 else 0), index=int(v))
+                                  for N, v in zip(sizes, variants)},
+                     "plan_candidates_ms": {k: round(v * 1e3, 5) for k, v in cand.items()}}
         del trip, outs, cap
         torch.cuda.empty_cache()
     return res
@@ -329,6 +385,9 @@ def main():
 
     ms, per = time_launches(step, args.steps, args.warmup, torch)
     kern_ms = float(np.mean(per))
+    q1, med, q3 = (float(x) for x in np.percentile(per, [25, 50, 75]))
+    ncpu = min(args.cpu_elements, K)
+    samples = {"fp64_headline": out[:, :ncpu].cpu().numpy()} if not args.no_cpu else {}
     dofs = K * F * Np
     bytes_launch = K * fwd_bytes_per_element(F, Np)
     flops_launch = K * fwd_flops_per_element(F, Np)
@@ -363,7 +422,11 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "fp64_order4_K1048576_F5", "order": N, "Np": Np, "K": K, "F": F,
-                   "u": "N(0,1)", "mesh": "unit tet + U(-0.2,0.2) vertex jitter"},
+                   "u": "N(0,1)", "mesh": "unit tet + U(-0.2,0.2) vertex jitter",
+                   "seeds": {"mesh": synth.mesh_seed(2), "fields": synth.field_seed(2)}},
+        "timing": {"per_launch_ms_median": round(med, 5), "per_launch_ms_iqr": [round(q1, 5), round(q3, 5)],
+                   "clock": "HIP events on the launch stream"},
+        "revision": {"git": git_revision(), "source_sha256": source_sha()},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": recorded_traffic(),
                      "kernel_ms": round(kern_ms, 5),
@@ -385,11 +448,26 @@ def main():
         ms32, per32 = time_launches(lambda: dgvol.dg_volume_f32s(D32, G32, u32, out=o32), 20, 3, torch,
                                     min_warm_ms=WARM_MS)
         k32 = float(np.mean(per32))
+        # accuracy of the timed output (outside the timed region), every output, per plane:
+        # against the FP64 result on the FP64 data, and on the FP32-rounded inputs promoted to
+        # FP64 (isolates the arithmetic from the storage rounding); the FP64 results are the
+        # FP64 kernel's, which matches the oracle to 1e-12 (parity tests)
+        ref64 = dgvol.dg_volume(Dd, Gd, ud)
+        err64 = split_errors_gpu(o32, ref64, torch)
+        del ref64
+        ref32 = dgvol.dg_volume(D32.double(), G32.double(), u32.double())
+        err32 = split_errors_gpu(o32, ref32, torch)
+        del ref32
+        if samples:
+            samples["f32s_split_bf16"] = o32[:, :ncpu].cpu().numpy()
         forms["f32s_split_bf16_same_workload"] = {
             "GDOF/s": round(dofs / (ms32 * 1e-3) / 1e9, 3), "kernel_ms": round(k32, 5),
             "hbm_GBs": round(K * fwd_bytes_per_element(F, Np, 4) / (k32 * 1e-3) / 1e9, 1),
             "hbm_frac": round(K * fwd_bytes_per_element(F, Np, 4) / (k32 * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
-            "speedup_vs_fp64": round(ms / ms32, 3)}
+            "speedup_vs_fp64": round(ms / ms32, 3),
+            "error_per_plane_xyz": {"reference": "FP64 kernel, every output",
+                                    "vs_fp64_on_fp64_data": err64, "vs_fp64_on_fp32_rounded_inputs": err32,
+                                    "stated_bound": {"max_rel": 2e-5, "rms_rel": 1e-5}}}
         del D32, G32, u32, o32, Dd, Gd, ud
         torch.cuda.empty_cache()
         # adjoint workload: order 5, K = 2^19, F = 3, gout = 2 out
@@ -450,7 +528,7 @@ def main():
 
     if not args.no_cpu:
         n = min(args.cpu_elements, K)
-        rec["cpu_baseline"] = cpu_baseline(D, G[:n], u[:n])
+        rec["cpu_baseline"] = cpu_baseline(D, G[:n], u[:n], samples=samples)
     print(json.dumps(rec), flush=True)
 
 

@@ -57,16 +57,19 @@ typedef int32_t dg_status;
 #define DG_ELAUNCH (-3)       /* the HIP launch reported an error */
 #define DG_EDEVICE (-4)       /* querying the current device failed */
 
-#define DGVOL_ABI_VERSION 1
+#define DGVOL_ABI_VERSION 2
 
 /* Forms (precisions) of the forward product. */
 #define DG_FORM_F64 0   /* FP64 storage, FP64 matrix cores */
 #define DG_FORM_F32S 1  /* FP32 storage, split-BF16 matrix cores (see dg_volume_f32s) */
 
 /* Kernel bodies of the forward product (same results, different data movement). */
-#define DG_BODY_AUTO (-1)     /* the library's default for the form and order */
 #define DG_BODY_STAGED 0      /* D in LDS, u and out staged through LDS per wave (memory-bound orders) */
 #define DG_BODY_CHUNKREG 1    /* D held in registers, one output chunk per wave (matrix-core-bound orders) */
+#define DG_BODY_STAGED_LEAN 2 /* as STAGED with at most 128 registers a lane (two 8-wave workgroups per CU) */
+
+/* Variant (launch shape) selection: DG_VARIANT_AUTO is the library's default. */
+#define DG_VARIANT_AUTO (-1)
 
 #define DG_MAX_GROUPS 16
 
@@ -151,7 +154,7 @@ dg_status dg_volume_f32s(const float *D, const float *G, const float *u, float *
  */
 typedef struct dg_group {
   int32_t Np;          /* node count of the group's order */
-  int32_t body;        /* DG_BODY_AUTO, DG_BODY_STAGED or DG_BODY_CHUNKREG */
+  int32_t variant;     /* DG_VARIANT_AUTO or an index < dg_variant_count(form, Np) */
   int64_t K;           /* elements in the group (>= 0; 0 = skip) */
   const void *D;       /* [3][Np][Np] */
   const void *G;       /* [K][9] */
@@ -165,7 +168,10 @@ typedef struct dg_group {
 
 /*
  * Forward volume derivative of up to DG_MAX_GROUPS element groups of
- * possibly different orders, sharing F, in ONE persistent kernel launch.
+ * possibly different orders, sharing F, in one persistent kernel launch per
+ * variant class: each group runs its variant (dg_variant_info.batch_class
+ * names the batched kernel that holds it), and a batch whose groups fall into
+ * several classes makes one launch per class, in class order, on `stream`.
  * `groups` is a host array of `ngroups` descriptors; it is read during the
  * call only.  The resident workgroups are split between groups by cost x tiles,
  * so that the largest cost per workgroup is as small as possible (every group
@@ -174,16 +180,76 @@ typedef struct dg_group {
  * dg_volume_f32s would write for that group alone.
  * Errors: DG_EINVAL (ngroups outside 0..DG_MAX_GROUPS, F < 1, NULL groups
  * with ngroups > 0, a group failing the dg_volume argument checks),
- * DG_EUNSUPPORTED (form, Np or a body not available for the form and order),
+ * DG_EUNSUPPORTED (form, Np or a variant not available for the form and order),
  * DG_EDEVICE, DG_ELAUNCH.  Groups with K = 0 are skipped.
  */
 dg_status dg_volume_batched(const dg_group *groups, int32_t ngroups, int32_t F, int32_t form, void *stream);
 
-/* 1 if `body` can run `form` at node count Np, else 0. */
-int32_t dg_body_available(int32_t form, int32_t Np, int32_t body);
+/*
+ * Launch shapes ("variants") of the forward product.  For each form and node
+ * count the library is compiled with a short list of shapes that give the same
+ * result with different data movement: the body (DG_BODY_STAGED: D in LDS,
+ * every wave owns whole 16-column tiles; DG_BODY_CHUNKREG: D in registers,
+ * the workgroup shares its tiles), the waves per workgroup, and the 16-column
+ * tiles one loop iteration takes (per wave for the staged body, per workgroup
+ * for the chunk-register body).  Variant 0 is the default that dg_volume and
+ * dg_volume_f32s use; the others are the autotuner's search space (the paper's
+ * autotuning use case, Introduction and Section 3, applied to tile shapes).
+ */
+typedef struct dg_variant_info {
+  int32_t body;          /* DG_BODY_STAGED, DG_BODY_CHUNKREG or DG_BODY_STAGED_LEAN */
+  int32_t waves;         /* waves (64 lanes) per workgroup */
+  int32_t tiles;         /* 16-column tiles per loop iteration (per wave if staged, per workgroup if chunk-register) */
+  int32_t batch_class;   /* the batched kernel that runs it inside dg_volume_batched (0..2) */
+  int32_t lds_bytes;     /* dynamic LDS per workgroup */
+} dg_variant_info;
 
-/* The body DG_BODY_AUTO selects for `form` at node count Np (-1 if unsupported). */
-int32_t dg_default_body(int32_t form, int32_t Np);
+/* Number of variants for (form, Np); 0 if either is unsupported.  Pure host. */
+int32_t dg_variant_count(int32_t form, int32_t Np);
+
+/* Describe variant `variant` of (form, Np) into *info (host memory).  Pure host.
+ * Errors: DG_EINVAL (info NULL), DG_EUNSUPPORTED (form, Np or variant out of range). */
+dg_status dg_variant_query(int32_t form, int32_t Np, int32_t variant, dg_variant_info *info);
+
+/*
+ * Forward product with an explicit variant: `form` DG_FORM_F64 (double
+ * arrays, as dg_volume) or DG_FORM_F32S (float arrays, as dg_volume_f32s);
+ * `variant` DG_VARIANT_AUTO or an index < dg_variant_count(form, Np).  The
+ * result meets the same bound as the form's default entry point (FP64: the
+ * same reference values up to summation order; split-BF16: the same stated
+ * bound).  Errors as for dg_volume, plus DG_EUNSUPPORTED for the variant.
+ */
+dg_status dg_volume_variant(int32_t form, int32_t variant, const void *D, const void *G, const void *u,
+                            void *out, int64_t K, int32_t Np, int32_t F, void *stream);
+
+/*
+ * Launch shape of an operation on the current device, computed on the host
+ * without launching anything (it queries the device's occupancy for the
+ * kernel).  A work unit is a 16-column tile for the forward operations, and
+ * a tile of whole elements (16/F of them, or one element in ceil(F/16)
+ * sub-tiles) for the adjoint.  min_iters is the loop iterations of the
+ * least-loaded wave (the persistent loops hand out units round-robin), taken
+ * over every kernel the operation launches.
+ */
+typedef struct dg_launch_shape {
+  uint32_t grid;            /* workgroups launched (first kernel of the operation) */
+  uint32_t block;           /* threads per workgroup */
+  uint32_t lds_bytes;       /* dynamic LDS per workgroup */
+  uint32_t resident;        /* workgroups the device holds at once (the persistent grid cap) */
+  uint32_t units;           /* work units of the problem */
+  uint32_t units_per_step;  /* units one workgroup takes per loop iteration */
+  uint32_t min_iters;       /* loop iterations of the least-loaded wave, over the operation's kernels */
+  uint32_t max_iters;       /* loop iterations of the most-loaded wave, over the operation's kernels */
+} dg_launch_shape;
+
+#define DG_OP_FORWARD 0   /* dg_volume_variant(form, variant, ...) */
+#define DG_OP_BATCHED 1   /* dg_volume_batched with one group of this (Np, variant) */
+#define DG_OP_ADJOINT 2   /* dg_volume_adjoint (form must be DG_FORM_F64; variant ignored) */
+
+/* Errors: DG_EINVAL (shape NULL, op unknown, K < 1, F < 1), DG_EUNSUPPORTED
+ * (form, Np or variant), DG_EDEVICE. */
+dg_status dg_launch_shape_query(int32_t op, int32_t form, int32_t Np, int32_t variant, int64_t K, int32_t F,
+                                dg_launch_shape *shape);
 
 /*
  * Bandwidth calibration (not part of the DG computation).
@@ -192,8 +258,11 @@ int32_t dg_default_body(int32_t form, int32_t Np);
  * With copies = 1 it is a plain copy of known size, used to scale hardware
  * byte counters; with copies = 3 it moves bytes in the same 1 : 3 read : write
  * mix as dg_volume with no other work, which measures the practical streaming
- * ceiling for that mix.  Errors: DG_EINVAL (n < 0, copies outside 1..3, null
- * or misaligned pointer with n > 0), DG_EDEVICE, DG_ELAUNCH.
+ * ceiling for that mix.  When src and dst are 16-byte aligned and n is even,
+ * every thread moves several independent 16-byte pairs in a one-pass grid;
+ * otherwise single words in a grid-stride loop.  Errors: DG_EINVAL (n < 0,
+ * copies outside 1..3, null or misaligned pointer with n > 0), DG_EDEVICE,
+ * DG_ELAUNCH.
  */
 dg_status dg_stream_calibrate(const double *src, double *dst, int64_t n, int32_t copies, void *stream);
 

@@ -1,11 +1,25 @@
-"""Autotuner for the mixed-order batched launch.
+"""Autotuner of the forward product's tile shapes (launch variants).
 
-For every (form, Np, F) it times each available kernel body
-(``dg_body_available``) as a one-group batched launch on a synthetic problem
-large enough to fill the GPU, keeps the fastest, and records the measured
-time of one 16-column tile.  That time is the ``cost`` the batched launch
-uses to split its persistent workgroups between groups, so the split follows
-measured rather than estimated work.
+The library is compiled with a short list of launch variants per (form, Np)
+(``dg_variant_count`` / ``dg_variant_query``): the body that moves the data
+(LDS-staged or chunk-register), the waves per workgroup and the 16-column
+tiles one loop iteration takes.  They compute the same result with different
+data movement; which is fastest depends on the order, the number of fields
+and the device.  This is the paper's autotuning use case (Introduction and
+Section 3: a search over the transformation parameters of a kernel) applied
+to those tile shapes.
+
+``tune(form, Np, F)`` times every variant on a synthetic problem large enough
+to fill the GPU, twice: as a single-group launch (``dg_volume_variant``) and
+as a one-group batched launch (the variant runs inside its class's batched
+kernel, whose register budget can differ), and records the fastest of each
+with the measured time of one 16-column tile.  That time is the ``cost`` the
+batched launch uses to split its persistent workgroups between groups.
+
+``plan_batch(groups, form)`` then measures whole candidate plans on the actual
+groups (the library default, the per-group tuned variants with measured
+costs, and the tuned variants with the library's cost estimate) and keeps the
+fastest, so a tuned batch is never slower than the default one as measured.
 
 Results are cached in a JSON file (``$DGVOL_AUTOTUNE_CACHE``, default
 ``~/.cache/dgvol/autotune.json``) keyed by the GPU architecture and the
@@ -24,7 +38,6 @@ from . import dgvol
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "dgvol", "autotune.json")
 FORM_NAMES = {dgvol.FORM_F64: "f64", dgvol.FORM_F32S: "f32s"}
-ORDER_OF_NP = {4: 1, 10: 2, 20: 3, 35: 4, 56: 5, 84: 6, 120: 7}
 
 
 def cache_path():
@@ -40,6 +53,10 @@ def device_key(device=None):
 
 def entry_key(form, Np, F):
     return f"{FORM_NAMES[form]}/Np{Np}/F{F}"
+
+
+def batch_key(form, groups):
+    return f"batch/{FORM_NAMES[form]}/" + ",".join(f"{u.shape[2]}x{u.shape[0]}x{u.shape[1]}" for _, _, u in groups)
 
 
 def load_cache(path=None):
@@ -64,9 +81,14 @@ def save_cache(data, path=None):
     os.replace(tmp, p)
 
 
-def _valid_entry(e):
-    return (isinstance(e, dict) and isinstance(e.get("body"), int) and
-            isinstance(e.get("tile_cost_s"), (int, float)) and e["tile_cost_s"] > 0)
+def _valid_entry(e, form, Np):
+    if not isinstance(e, dict):
+        return False
+    n = dgvol.variant_count(form, Np)
+    for k in ("variant", "single_variant"):
+        if not isinstance(e.get(k), int) or not 0 <= e[k] < n:
+            return False
+    return isinstance(e.get("tile_cost_s"), (int, float)) and e["tile_cost_s"] > 0
 
 
 def _synthetic(form, Np, F, K, device):
@@ -79,8 +101,8 @@ def _synthetic(form, Np, F, K, device):
     return D, G, u
 
 
-def _time_body(form, body, D, G, u, out, reps):
-    fn = lambda: dgvol.dg_volume_batched([(D, G, u)], form=form, outs=[out], bodies=[body])  # noqa: E731
+def _median_time(fn, reps):
+    """Median seconds of fn() over `reps` launches, timed with HIP events on the current stream."""
     fn()
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
@@ -94,7 +116,7 @@ def _time_body(form, body, D, G, u, out, reps):
 
 
 def tune(form, Np, F, target_bytes=256 << 20, min_tiles=1 << 15, reps=10, device=None, cache=None, save=True):
-    """Measure every available body for (form, Np, F); store and return the cache entry.
+    """Measure every variant of (form, Np) at F fields; store and return the cache entry.
 
     The problem moves at least ``target_bytes`` and holds at least ``min_tiles``
     16-column tiles, so that at the high orders (few bytes per unit of matrix
@@ -105,13 +127,18 @@ def tune(form, Np, F, target_bytes=256 << 20, min_tiles=1 << 15, reps=10, device
     D, G, u = _synthetic(form, Np, F, K, device)
     out = torch.empty((3, K, F, Np), dtype=u.dtype, device=device)
     ntiles = -(-K * F // 16)
-    times = {}
-    for body in (dgvol.BODY_STAGED, dgvol.BODY_CHUNKREG):
-        if dgvol.body_available(form, Np, body):
-            times[body] = _time_body(form, body, D, G, u, out, reps)
-    best = min(times, key=times.get)
-    entry = {"body": int(best), "tile_cost_s": times[best] / ntiles,
-             "candidates_s_per_tile": {str(b): t / ntiles for b, t in times.items()}, "K": K}
+    single, batched = {}, {}
+    for v in range(dgvol.variant_count(form, Np)):
+        single[v] = _median_time(lambda: dgvol.dg_volume_variant(form, v, D, G, u, out=out), reps)
+        batched[v] = _median_time(
+            lambda: dgvol.dg_volume_batched([(D, G, u)], form=form, outs=[out], variants=[v]), reps)
+    best_b = min(batched, key=batched.get)
+    best_s = min(single, key=single.get)
+    entry = {"variant": int(best_b), "tile_cost_s": batched[best_b] / ntiles,
+             "single_variant": int(best_s), "single_tile_cost_s": single[best_s] / ntiles,
+             "candidates_s_per_tile": {str(v): t / ntiles for v, t in batched.items()},
+             "single_candidates_s_per_tile": {str(v): t / ntiles for v, t in single.items()},
+             "shapes": {str(v): dgvol.variant_info(form, Np, v) for v in single}, "K": K}
     data = cache if cache is not None else load_cache()
     ns = data.setdefault(device_key(device), {})
     ns[entry_key(form, Np, F)] = entry
@@ -124,7 +151,7 @@ def lookup(form, Np, F, device=None, cache=None, tune_missing=True):
     """Cached entry for (form, Np, F); tuned on demand when missing and allowed."""
     data = cache if cache is not None else load_cache()
     e = data.get(device_key(device), {}).get(entry_key(form, Np, F))
-    if _valid_entry(e):
+    if _valid_entry(e, form, Np):
         return e
     if not tune_missing:
         return None
@@ -132,18 +159,48 @@ def lookup(form, Np, F, device=None, cache=None, tune_missing=True):
 
 
 def plan(groups, form=dgvol.FORM_F64, tune_missing=True):
-    """Bodies and tile costs for dg_volume_batched from the tuning cache."""
-    bodies, costs = [], []
+    """Per-group variants and measured tile costs for dg_volume_batched from the tuning cache."""
+    variants, costs = [], []
     data = load_cache()
     for D, G, u in groups:
         K, F, Np = u.shape
         e = lookup(form, Np, F, device=u.device, cache=data, tune_missing=tune_missing)
-        bodies.append(dgvol.BODY_AUTO if e is None else e["body"])
+        variants.append(dgvol.VARIANT_AUTO if e is None else e["variant"])
         costs.append(0.0 if e is None else e["tile_cost_s"])
-    return bodies, costs
+    return variants, costs
+
+
+def plan_batch(groups, form=dgvol.FORM_F64, outs=None, reps=10, tune_missing=True, save=True):
+    """The fastest measured plan (variants, costs) for this batch of groups.
+
+    Candidates: the library default (variant 0, estimated costs), the per-group
+    tuned variants with their measured costs, and the tuned variants with the
+    estimated costs.  Each is timed on the actual groups; the result is cached
+    under the batch's shapes.  Returns (variants, costs, {candidate: seconds})."""
+    device = groups[0][2].device
+    data = load_cache()
+    key = batch_key(form, groups)
+    ns = data.setdefault(device_key(device), {})
+    e = ns.get(key)
+    n = len(groups)
+    if isinstance(e, dict) and len(e.get("variants", [])) == n and len(e.get("costs", [])) == n:
+        return e["variants"], e["costs"], e.get("candidates_s", {})
+    if outs is None:
+        outs = [torch.empty((3,) + tuple(u.shape), dtype=u.dtype, device=device) for _, _, u in groups]
+    tv, tc = plan(groups, form, tune_missing=tune_missing)
+    cands = {"default": ([dgvol.VARIANT_AUTO] * n, [0.0] * n), "tuned": (tv, tc), "tuned_variants": (tv, [0.0] * n)}
+    times = {name: _median_time(lambda: dgvol.dg_volume_batched(groups, form=form, outs=outs, variants=v, costs=c),
+                                reps)
+             for name, (v, c) in cands.items()}
+    best = min(times, key=times.get)
+    ns[key] = {"variants": [int(x) for x in cands[best][0]], "costs": [float(x) for x in cands[best][1]],
+               "choice": best, "candidates_s": times}
+    if save:
+        save_cache(data)
+    return cands[best][0], cands[best][1], times
 
 
 def volume_batched_tuned(groups, form=dgvol.FORM_F64, outs=None):
-    """dg_volume_batched with the tuned body and measured cost of every group."""
-    bodies, costs = plan(groups, form)
-    return dgvol.dg_volume_batched(groups, form=form, outs=outs, bodies=bodies, costs=costs)
+    """dg_volume_batched with the fastest measured plan for these groups."""
+    variants, costs, _ = plan_batch(groups, form, outs=outs)
+    return dgvol.dg_volume_batched(groups, form=form, outs=outs, variants=variants, costs=costs)

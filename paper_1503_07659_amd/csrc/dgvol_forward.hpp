@@ -43,26 +43,33 @@ struct FwdArgs {
 
 // ------------------------------------------------------------------ FP64 staged
 
-// 16-column tiles a wave of the FP64 staged body takes per iteration.  A tile
-// of a low order is only 16 Np doubles, too few bytes in flight per wave to
-// cover the memory latency; several tiles per iteration (with their geometric
-// factors fetched as one contiguous run) raise that.
+// 16-column tiles a wave of the FP64 staged body takes per iteration (TPI),
+// by default.  A tile of a low order is only 16 Np doubles, too few bytes in
+// flight per wave to cover the memory latency; several tiles per iteration
+// (with their geometric factors fetched as one contiguous run) raise that.
+// Other counts are instantiated as tuning variants.
 template <int NP>
 constexpr int staged_tpi() { return NP <= 4 ? 4 : (NP <= 20 ? 2 : 1); }
 
 // Per wave: the u / output staging buffer, plus, with several tiles per
 // iteration, room for the geometric factors of up to 16 TPI elements.
-template <int NP>
+template <int NP, int TPI>
 constexpr int staged_wave_doubles() {
-  constexpr int TPI = staged_tpi<NP>();
   // (Np >= 56: rows padded to an odd stride, see fwd_f64_staged_early)
   return TPI * 16 * (NP >= 56 ? NP + 1 : NP) + (TPI > 1 ? TPI * 16 * 9 : 0);
 }
 
-template <int NP, int WPB>
-constexpr int fwd_f64_staged_lds() { return align16(fwd_table_doubles<NP>() * 8) + WPB * staged_wave_doubles<NP>() * 8; }
+template <int NP, int WPB, int TPI>
+constexpr int fwd_f64_staged_lds() {
+  return align16(fwd_table_doubles<NP>() * 8) + WPB * staged_wave_doubles<NP, TPI>() * 8;
+}
 
-template <int NP, int WPB>
+// LEAN: the register-lean form (two 8-wave workgroups per CU, at most 128
+// registers a lane): each A operand is read from LDS right before its product
+// instead of one k-step ahead, and the geometric factors are read after the
+// products instead of being held through them.  The other resident workgroup
+// covers the LDS latency this exposes.
+template <int NP, int WPB, bool LEAN = false>
 __device__ __forceinline__ void fwd_f64_staged_single(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
                                                       char* lds) {
   using Sh = Shape<NP>;
@@ -115,28 +122,43 @@ __device__ __forceinline__ void fwd_f64_staged_single(const FwdArgs<double>& p, 
     const bool valid = col < p.ncols;
     const uint32_t k = valid ? col / p.F : 0u;
     double gk[9];
+    if constexpr (!LEAN) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) gk[c] = valid ? p.G[(int64_t)k * 9 + c] : 0.0;
+      for (int c = 0; c < 9; ++c) gk[c] = valid ? p.G[(int64_t)k * 9 + c] : 0.0;
+    }
     wave_sync();
     f64x4 acc[Sh::MT];
 #pragma unroll
     for (int T = 0; T < Sh::MT; ++T) acc[T] = f64x4{0.0, 0.0, 0.0, 0.0};
-    // A operands are read one k-step ahead of the products that use them; the
-    // scheduling barrier keeps the compiler from hoisting every read (which
-    // would cost about two registers per MFMA).
-    double a_cur[Sh::MT], a_nxt[Sh::MT];
+    if constexpr (LEAN) {
 #pragma unroll
-    for (int T = 0; T < Sh::MT; ++T) a_cur[T] = afr[(T * Sh::KS64) * WAVE + lane];
+      for (int s = 0; s < Sh::KS64; ++s) {
 #pragma unroll
-    for (int s = 0; s < Sh::KS64; ++s) {
-#pragma unroll
-      for (int T = 0; T < Sh::MT; ++T) {
-        if (s + 1 < Sh::KS64) a_nxt[T] = afr[(T * Sh::KS64 + s + 1) * WAVE + lane];
-        acc[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[T], b[s], acc[T], 0, 0, 0);
+        for (int T = 0; T < Sh::MT; ++T)
+          acc[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[(T * Sh::KS64 + s) * WAVE + lane], b[s], acc[T], 0, 0,
+                                                       0);
+        __builtin_amdgcn_sched_barrier(0);
       }
-      __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int T = 0; T < Sh::MT; ++T) a_cur[T] = a_nxt[T];
+      for (int c = 0; c < 9; ++c) gk[c] = valid ? p.G[(int64_t)k * 9 + c] : 0.0;
+    } else {
+      // A operands are read one k-step ahead of the products that use them; the
+      // scheduling barrier keeps the compiler from hoisting every read (which
+      // would cost about two registers per MFMA).
+      double a_cur[Sh::MT], a_nxt[Sh::MT];
+#pragma unroll
+      for (int T = 0; T < Sh::MT; ++T) a_cur[T] = afr[(T * Sh::KS64) * WAVE + lane];
+#pragma unroll
+      for (int s = 0; s < Sh::KS64; ++s) {
+#pragma unroll
+        for (int T = 0; T < Sh::MT; ++T) {
+          if (s + 1 < Sh::KS64) a_nxt[T] = afr[(T * Sh::KS64 + s + 1) * WAVE + lane];
+          acc[T] = __builtin_amdgcn_mfma_f64_16x16x4f64(a_cur[T], b[s], acc[T], 0, 0, 0);
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int T = 0; T < Sh::MT; ++T) a_cur[T] = a_nxt[T];
+      }
     }
 #pragma unroll
     for (int bb = 0; bb < 3; ++bb) {
@@ -288,11 +310,10 @@ __device__ __forceinline__ void fwd_f64_staged_early(const FwdArgs<double>& p, u
 // and fetches the geometric factors of their elements, which are contiguous in
 // G, as one run too.  Both are loaded into registers one iteration ahead and
 // staged through the wave's LDS buffer.
-template <int NP, int WPB>
+template <int NP, int WPB, int TPI>
 __device__ __forceinline__ void fwd_f64_staged_multi(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
                                                      char* lds) {
   using Sh = Shape<NP>;
-  constexpr int TPI = staged_tpi<NP>();
   constexpr int NFRAG = fwd_table_doubles<NP>();
   constexpr int TILE = 16 * NP;
   constexpr int RUN = TPI * TILE;                  // doubles of u per iteration
@@ -308,7 +329,7 @@ __device__ __forceinline__ void fwd_f64_staged_multi(const FwdArgs<double>& p, u
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  double* su = reinterpret_cast<double*>(lds + align16(NFRAG * 8)) + wave * staged_wave_doubles<NP>();
+  double* su = reinterpret_cast<double*>(lds + align16(NFRAG * 8)) + wave * staged_wave_doubles<NP, TPI>();
   double* sg = su + RUN;
   const uint32_t nrun = (p.ntiles + TPI - 1) / TPI;
   const uint32_t stride = nblk * WPB;
@@ -419,11 +440,13 @@ __device__ __forceinline__ void fwd_f64_staged_multi(const FwdArgs<double>& p, u
   }
 }
 
-template <int NP, int WPB>
+template <int NP, int WPB, int TPI, bool LEAN = false>
 __device__ __forceinline__ void fwd_f64_staged_body(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
                                                     char* lds) {
-  if constexpr (staged_tpi<NP>() > 1)
-    fwd_f64_staged_multi<NP, WPB>(p, bid, nblk, lds);
+  if constexpr (LEAN)
+    fwd_f64_staged_single<NP, WPB, true>(p, bid, nblk, lds);
+  else if constexpr (TPI > 1)
+    fwd_f64_staged_multi<NP, WPB, TPI>(p, bid, nblk, lds);
   else if constexpr (NP >= 56)
     fwd_f64_staged_early<NP, WPB>(p, bid, nblk, lds);
   else
@@ -445,9 +468,10 @@ constexpr int chunk_ld() { return WORD == 8 ? NP + 1 : ((NP + 3) / 8) * 8 + 4; }
 template <int NP, int WORD>
 constexpr int chunk_old() { return WORD == 8 ? NP + 2 : ((NP + 3) / 8) * 8 + 4; }
 
-// Column tiles the workgroup shares per iteration of the chunk-register bodies:
-// more tiles per iteration means fewer barriers per byte and more bytes in flight,
-// at the cost of prefetch registers (FP64 at Np = 120 has none to spare).
+// Column tiles the workgroup shares per iteration of the chunk-register bodies
+// (TPW), by default: more tiles per iteration means fewer barriers per byte and
+// more bytes in flight, at the cost of prefetch registers (FP64 at Np = 120
+// has none to spare).  Other counts are instantiated as tuning variants.
 template <int NP, int WORD>
 constexpr int chunk_tpw() { return WORD == 4 ? 4 : (NP >= 120 ? 1 : 2); }
 
@@ -459,21 +483,19 @@ template <int NP>
 constexpr int chunk_ldb() { return Shape<NP>::KS16 * 32 + 8; }
 
 // Bytes of the staged u of one iteration.
-template <int NP, int WORD>
+template <int NP, int WORD, int TPW>
 constexpr int chunk_us_bytes() {
-  constexpr int TPW = chunk_tpw<NP, WORD>();
   return WORD == 8 ? TPW * 16 * chunk_ld<NP, WORD>() * WORD : 2 * TPW * 16 * chunk_ldb<NP>() * 2;
 }
 
-template <int NP, int WORD>
+template <int NP, int WORD, int TPW>
 constexpr int chunk_lds() {
-  constexpr int TPW = chunk_tpw<NP, WORD>();
-  return align16(chunk_us_bytes<NP, WORD>()) + align16(3 * TPW * 16 * chunk_old<NP, WORD>() * WORD) +
+  return align16(chunk_us_bytes<NP, WORD, TPW>()) + align16(3 * TPW * 16 * chunk_old<NP, WORD>() * WORD) +
          TPW * 16 * 9 * WORD;
 }
 
-template <int NP, int WPB>
-constexpr int fwd_f64_chunkreg_lds() { return chunk_lds<NP, 8>(); }
+template <int NP, int WPB, int TPW>
+constexpr int fwd_f64_chunkreg_lds() { return chunk_lds<NP, 8, TPW>(); }
 
 // Shared skeleton of the chunk-register bodies.  Per iteration the workgroup
 // stages TPW consecutive 16-column tiles of u (padded rows) and the geometric
@@ -487,11 +509,10 @@ constexpr int fwd_f64_chunkreg_lds() { return chunk_lds<NP, 8>(); }
 // previous iteration's stores (order 7 took 13 % longer).  The body lays out
 // the staged u: put_u(us, column, node, value) stores one word of it (FP64:
 // padded rows; split-BF16: the value split into BF16 hi and lo planes).
-template <typename T, int NP, int WPB, int KS, int VEC, typename ChunkFn, typename PutU>
+template <typename T, int NP, int WPB, int KS, int TPW, int VEC, typename ChunkFn, typename PutU>
 __device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t bid, uint32_t nblk, char* lds,
                                                   ChunkFn&& chunk, PutU&& put_u) {
   constexpr int WORD = sizeof(T);
-  constexpr int TPW = chunk_tpw<NP, WORD>();
   constexpr int SUP = TPW * 16 * NP;        // words of one plane of the super-tile
   constexpr int OLD = chunk_old<NP, WORD>();
   constexpr int OSUP = TPW * 16 * OLD;      // words of one plane of the output tile
@@ -501,8 +522,8 @@ __device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t 
   constexpr int GMAX = TPW * 16 * 9;        // geometric-factor words of at most TPW*16 elements
   constexpr int NG = (GMAX + NT - 1) / NT;  // G words loaded per thread per iteration
   char* us = lds;  // laid out by put_u (the body's staging of one u word)
-  T* ostg = reinterpret_cast<T*>(lds + align16(chunk_us_bytes<NP, WORD>()));
-  T* gs = reinterpret_cast<T*>(lds + align16(chunk_us_bytes<NP, WORD>()) + align16(3 * OSUP * WORD));
+  T* ostg = reinterpret_cast<T*>(lds + align16(chunk_us_bytes<NP, WORD, TPW>()));
+  T* gs = reinterpret_cast<T*>(lds + align16(chunk_us_bytes<NP, WORD, TPW>()) + align16(3 * OSUP * WORD));
   const int tid = threadIdx.x;
   const uint32_t nsup = (p.ntiles + TPW - 1) / TPW;
   T ur[NLD][VEC];
@@ -584,27 +605,26 @@ __device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t 
 // of them and u, out start 16-byte aligned (planes then are too); single words
 // otherwise.  Measured: pairs -4 % (order 7) and -5 % (order 6); four-float
 // vectors made the split-BF16 body 2-3 % slower, so it moves single words.
-template <typename T, int NP, int WPB, int KS, typename ChunkFn, typename PutU>
+template <typename T, int NP, int WPB, int KS, int TPW, typename ChunkFn, typename PutU>
 __device__ __forceinline__ void chunkreg_loop(const FwdArgs<T>& p, uint32_t bid, uint32_t nblk, char* lds,
                                               ChunkFn&& chunk, PutU&& put_u) {
   constexpr int V = sizeof(T) == 8 ? 2 : 1;
   if constexpr (V > 1 && NP % V == 0) {
     if ((((uintptr_t)p.u | (uintptr_t)p.out) & 15u) == 0) {
-      chunkreg_loop_vec<T, NP, WPB, KS, V>(p, bid, nblk, lds, chunk, put_u);
+      chunkreg_loop_vec<T, NP, WPB, KS, TPW, V>(p, bid, nblk, lds, chunk, put_u);
       return;
     }
   }
-  chunkreg_loop_vec<T, NP, WPB, KS, 1>(p, bid, nblk, lds, chunk, put_u);
+  chunkreg_loop_vec<T, NP, WPB, KS, TPW, 1>(p, bid, nblk, lds, chunk, put_u);
 }
 
-template <int NP, int WPB>
+template <int NP, int WPB, int TPW>
 __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, uint32_t bid, uint32_t nblk,
                                                       char* lds) {
   using Sh = Shape<NP>;
   static_assert(WPB >= Sh::NCHUNK, "one wave per output chunk");
   constexpr int KS = Sh::KS64;
   constexpr int LD = chunk_ld<NP, 8>();
-  constexpr int TPW = chunk_tpw<NP, 8>();
   constexpr int OLD = chunk_old<NP, 8>();
   constexpr int OSUP = TPW * 16 * OLD;
   const int lane = threadIdx.x & 63;
@@ -661,7 +681,7 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
       }
     }
   };
-  chunkreg_loop<double, NP, WPB, KS>(p, bid, nblk, lds, chunk, put_u);
+  chunkreg_loop<double, NP, WPB, KS, TPW>(p, bid, nblk, lds, chunk, put_u);
 }
 
 }  // namespace dgvol

@@ -17,21 +17,21 @@ namespace dgvol {
 template <int NP>
 constexpr bool bf16_table_fits() { return bf16_table_entries<NP>() * 32 <= 96 * 1024; }
 
-// Tiles per wave iteration of the split-BF16 staged body: FP32 words halve the
-// bytes of a tile, so more tiles per iteration than in FP64 are needed to keep
-// enough bytes in flight.
+// Tiles per wave iteration of the split-BF16 staged body (TPI), by default:
+// FP32 words halve the bytes of a tile, so more tiles per iteration than in
+// FP64 are needed to keep enough bytes in flight.  Other counts are
+// instantiated as tuning variants.
 template <int NP>
 constexpr int f32s_tpi() { return NP <= 4 ? 8 : (NP <= 20 ? 4 : (NP <= 35 ? 2 : 1)); }
 
-template <int NP>
+template <int NP, int TPI>
 constexpr int f32s_wave_floats() {
-  constexpr int TPI = f32s_tpi<NP>();
   return TPI * 16 * NP + (TPI > 1 ? TPI * 16 * 9 : 0);
 }
 
-template <int NP, int WPB>
+template <int NP, int WPB, int TPI>
 constexpr int fwd_f32s_staged_lds() {
-  return (bf16_table_fits<NP>() ? 2 * bf16_table_entries<NP>() * 16 : 0) + WPB * f32s_wave_floats<NP>() * 4;
+  return (bf16_table_fits<NP>() ? 2 * bf16_table_entries<NP>() * 16 : 0) + WPB * f32s_wave_floats<NP, TPI>() * 4;
 }
 
 // u, out and every plane start 8-byte aligned: the staged split-BF16 body then
@@ -183,11 +183,10 @@ __device__ __forceinline__ void fwd_f32s_staged_single(const FwdArgs<float>& p, 
 // takes TPI consecutive tiles, one contiguous run of u and of each plane (moved
 // as float pairs when aligned), and the geometric factors of their elements
 // as one run.
-template <int NP, int WPB>
+template <int NP, int WPB, int TPI>
 __device__ __forceinline__ void fwd_f32s_staged_multi(const FwdArgs<float>& p, uint32_t bid, uint32_t nblk,
                                                       char* lds) {
   using Sh = Shape<NP>;
-  constexpr int TPI = f32s_tpi<NP>();
   constexpr bool ALDS = bf16_table_fits<NP>();
   constexpr int NTE = ALDS ? bf16_table_entries<NP>() : 0;
   constexpr int TILE = 16 * NP;
@@ -213,7 +212,7 @@ __device__ __forceinline__ void fwd_f32s_staged_multi(const FwdArgs<float>& p, u
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
   const uint32_t wave = threadIdx.x >> 6;
-  float* su = reinterpret_cast<float*>(lds + 2 * NTE * 16) + wave * f32s_wave_floats<NP>();
+  float* su = reinterpret_cast<float*>(lds + 2 * NTE * 16) + wave * f32s_wave_floats<NP, TPI>();
   float* sg = su + RUN;
   const uint32_t nrun = (p.ntiles + TPI - 1) / TPI;
   const uint32_t stride = nblk * WPB;
@@ -360,27 +359,26 @@ __device__ __forceinline__ void fwd_f32s_staged_multi(const FwdArgs<float>& p, u
   }
 }
 
-template <int NP, int WPB>
+template <int NP, int WPB, int TPI>
 __device__ __forceinline__ void fwd_f32s_staged_body(const FwdArgs<float>& p, uint32_t bid, uint32_t nblk,
                                                      char* lds) {
-  if constexpr (f32s_tpi<NP>() > 1)
-    fwd_f32s_staged_multi<NP, WPB>(p, bid, nblk, lds);
+  if constexpr (TPI > 1)
+    fwd_f32s_staged_multi<NP, WPB, TPI>(p, bid, nblk, lds);
   else
     fwd_f32s_staged_single<NP, WPB>(p, bid, nblk, lds);
 }
 
 // ------------------------------------------------------------------ split-BF16 chunk-register
 
-template <int NP, int WPB>
-constexpr int fwd_f32s_chunkreg_lds() { return chunk_lds<NP, 4>(); }
+template <int NP, int WPB, int TPW>
+constexpr int fwd_f32s_chunkreg_lds() { return chunk_lds<NP, 4, TPW>(); }
 
-template <int NP, int WPB>
+template <int NP, int WPB, int TPW>
 __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, uint32_t bid, uint32_t nblk,
                                                        char* lds) {
   using Sh = Shape<NP>;
   static_assert(WPB >= Sh::NCHUNK, "one wave per output chunk");
   constexpr int KS = Sh::KS16;
-  constexpr int TPW = chunk_tpw<NP, 4>();
   constexpr int OLD = chunk_old<NP, 4>();
   constexpr int OSUP = TPW * 16 * OLD;
   const int lane = threadIdx.x & 63;
@@ -458,7 +456,7 @@ __device__ __forceinline__ void fwd_f32s_chunkreg_body(const FwdArgs<float>& p, 
       }
     }
   };
-  chunkreg_loop<float, NP, WPB, KS>(p, bid, nblk, lds, chunk, put_u);
+  chunkreg_loop<float, NP, WPB, KS, TPW>(p, bid, nblk, lds, chunk, put_u);
 }
 
 }  // namespace dgvol

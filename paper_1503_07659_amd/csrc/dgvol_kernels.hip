@@ -15,6 +15,7 @@
 #include <atomic>
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "dgvol.h"
 #include "dgvol_adjoint.hpp"
@@ -57,193 +58,147 @@ static int cu_count(int dev, int* err) {
 }
 
 // Resident workgroups of `kernel` on the whole device (the persistent grid
-// size).  Kernels that take all their LDS dynamically (dyn_lds >= 0) get their
-// dynamic-LDS limit raised to the full 160 KiB, and are queried with the
-// largest size of the request's class (so a cached count is never too large);
-// kernels with static LDS only (dyn_lds < 0) are queried as they are.  The
-// result is cached per kernel instance, device and class.
-template <typename Kern>
-static int resident_blocks(Kern kernel, int block, int dyn_lds, int* err) {
-  static std::atomic<int> cache[MAX_DEVICES][5];
+// size) for a launch of `block` threads with `dyn_lds` bytes of dynamic LDS
+// (dyn_lds < 0: the kernel has static LDS only).  A kernel with dynamic LDS
+// gets its limit raised to the full 160 KiB before its first query on a
+// device.  Counts are cached per (device, kernel address, block size, LDS
+// bytes) in a small table, so every kernel instance has entries of its own
+// and the occupancy of one instance never sets the grid of another.
+struct OccEntry {
+  int dev;
+  const void* fn;
+  int block;
+  int lds;
+  int total;
+};
+constexpr int OCC_SLOTS = 1024;
+static std::mutex occ_mutex;
+static OccEntry occ_table[OCC_SLOTS];
+static int occ_used = 0;
+
+static int resident_blocks_fn(const void* fn, int block, int dyn_lds, int* err) {
   const int dev = current_device(err);
   if (dev < 0) return 0;
-  const int cls = dyn_lds < 0 ? 4 : dyn_lds <= 40960 ? 0 : dyn_lds <= 81920 ? 1 : dyn_lds <= 122880 ? 2 : 3;
-  if (dev < MAX_DEVICES) {
-    const int c = cache[dev][cls].load(std::memory_order_relaxed);
-    if (c > 0) return c;
+  bool attr_set = false;
+  {
+    std::lock_guard<std::mutex> lock(occ_mutex);
+    for (int i = 0; i < occ_used; ++i) {
+      const OccEntry& e = occ_table[i];
+      if (e.dev != dev || e.fn != fn) continue;
+      attr_set = true;
+      if (e.block == block && e.lds == dyn_lds) return e.total;
+    }
   }
   const int cus = cu_count(dev, err);
   if (*err != DG_OK) return 0;
-  int probe = 0;
-  if (dyn_lds >= 0) {
+  if (dyn_lds >= 0 && !attr_set) {
     // a failure here surfaces as a launch error of a kernel asking for more than the default limit
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
-                              160 * 1024);
-    probe = cls == 0 ? 40960 : cls == 1 ? 81920 : cls == 2 ? 122880 : 160 * 1024;
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
   }
   int per_cu = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, block, probe) != hipSuccess || per_cu <= 0)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, block, dyn_lds < 0 ? 0 : dyn_lds) != hipSuccess ||
+      per_cu <= 0)
     per_cu = 1;
   const int total = cus * per_cu;
-  if (dev < MAX_DEVICES) cache[dev][cls].store(total, std::memory_order_relaxed);
+  std::lock_guard<std::mutex> lock(occ_mutex);
+  if (occ_used < OCC_SLOTS) occ_table[occ_used++] = OccEntry{dev, fn, block, dyn_lds, total};
   return total;
+}
+
+template <typename Kern>
+static int resident_blocks(Kern kernel, int block, int dyn_lds, int* err) {
+  return resident_blocks_fn(reinterpret_cast<const void*>(kernel), block, dyn_lds, err);
 }
 
 static inline uint32_t ceil_div(uint64_t a, uint64_t b) { return (uint32_t)((a + b - 1) / b); }
 
-// Default body per order: LDS-staged where memory bounds the problem and D
-// fits LDS, chunk-register where the matrix cores bound it.
-static int default_body_f64(int Np) { return Np <= 56 ? BODY_STAGED : BODY_CHUNKREG; }
-static int default_body_f32s(int Np) { return Np <= 84 ? BODY_STAGED : BODY_CHUNKREG; }
+// ------------------------------------------------------------------ forward variants
 
-static bool body_ok_f64(int Np, int body) {
-  if (body == BODY_CHUNKREG) return true;
-  if (body != BODY_STAGED) return false;
-  switch (Np) {
-    case 4: return f64_staged_ok<4>();
-    case 10: return f64_staged_ok<10>();
-    case 20: return f64_staged_ok<20>();
-    case 35: return f64_staged_ok<35>();
-    case 56: return f64_staged_ok<56>();
-    default: return false;
+// One compiled variant of the forward product (dgvol_variants.hpp).
+struct VariantDesc {
+  const void* fn;  // its single-group kernel
+  int body;
+  int wpb;
+  int tiles;
+  int cls;
+  int lds;
+};
+
+static bool variant_desc(int form, int Np, int v, VariantDesc* d) {
+#define DGVOL_VDESC64(NP, IDX, BODY, WPB, TILES, CLS)                                                   \
+  case vkey(NP, IDX):                                                                                   \
+    *d = VariantDesc{reinterpret_cast<const void*>(fwd_f64_kernel<NP, BODY, WPB, TILES>), BODY, WPB, TILES, \
+                     CLS, f64_lds<NP, BODY, WPB, TILES>()};                                             \
+    return true;
+#define DGVOL_VDESC32(NP, IDX, BODY, WPB, TILES, CLS)                                                    \
+  case vkey(NP, IDX):                                                                                    \
+    *d = VariantDesc{reinterpret_cast<const void*>(fwd_f32s_kernel<NP, BODY, WPB, TILES>), BODY, WPB, TILES, \
+                     CLS, f32s_lds<NP, BODY, WPB, TILES>()};                                             \
+    return true;
+  if (v < 0 || v >= 16) return false;
+  if (form == DG_FORM_F64) {
+    switch (vkey(Np, v)) { DGVOL_F64_VARIANTS(DGVOL_VDESC64) default: return false; }
   }
-}
-static bool body_ok_f32s(int, int body) { return body == BODY_STAGED || body == BODY_CHUNKREG; }
-
-template <int NP>
-static int lds_f64(int body) {
-  if constexpr (f64_staged_ok<NP>())
-    return body == BODY_STAGED ? f64_lds<NP, BODY_STAGED>() : f64_lds<NP, BODY_CHUNKREG>();
-  else
-    return f64_lds<NP, BODY_CHUNKREG>();
-}
-template <int NP>
-static int lds_f32s(int body) {
-  return body == BODY_STAGED ? f32s_lds<NP, BODY_STAGED>() : f32s_lds<NP, BODY_CHUNKREG>();
-}
-
-static int lds_bytes(int form, int Np, int body) {
-#define DGVOL_LDS(NPV) \
-  case NPV: return form == DG_FORM_F64 ? lds_f64<NPV>(body) : lds_f32s<NPV>(body);
-  switch (Np) {
-    DGVOL_LDS(4)
-    DGVOL_LDS(10)
-    DGVOL_LDS(20)
-    DGVOL_LDS(35)
-    DGVOL_LDS(56)
-    DGVOL_LDS(84)
-    DGVOL_LDS(120)
+  if (form == DG_FORM_F32S) {
+    switch (vkey(Np, v)) { DGVOL_F32S_VARIANTS(DGVOL_VDESC32) default: return false; }
   }
-#undef DGVOL_LDS
-  return 0;
+  return false;
+#undef DGVOL_VDESC64
+#undef DGVOL_VDESC32
 }
 
-// 16-column tiles one workgroup processes per step of its loop.
-static inline uint32_t tiles_per_block(int form, int Np, int body) {
-  if (body == BODY_STAGED) {
-    if (form == DG_FORM_F64) return FWD_WPB * (Np <= 4 ? staged_tpi<4>() : Np <= 20 ? staged_tpi<20>() : 1);
-    return FWD_WPB * (Np <= 4 ? f32s_tpi<4>() : Np <= 20 ? f32s_tpi<20>() : Np <= 35 ? f32s_tpi<35>() : 1);
-  }
-  if (form != DG_FORM_F64) return chunk_tpw<4, 4>();
-  return Np >= 120 ? chunk_tpw<120, 8>() : chunk_tpw<4, 8>();
+static int variant_count(int form, int Np) {
+  int c = 0;
+#define DGVOL_VCOUNT(NP, IDX, BODY, WPB, TILES, CLS) \
+  if (NP == Np) ++c;
+  if (form == DG_FORM_F64) { DGVOL_F64_VARIANTS(DGVOL_VCOUNT) }
+  if (form == DG_FORM_F32S) { DGVOL_F32S_VARIANTS(DGVOL_VCOUNT) }
+#undef DGVOL_VCOUNT
+  return c;
 }
 
-template <typename Kern, typename Args>
-static dg_status launch_persistent(Kern kern, const Args& args, uint32_t ntiles, int form, int Np, int body,
-                                   int lds, hipStream_t stream) {
-  int err = DG_OK;
-  const int cap = resident_blocks(kern, WAVE * FWD_WPB, lds, &err);
-  if (err != DG_OK) return err;
-  const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, tiles_per_block(form, Np, body)), (uint32_t)cap);
-  hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * FWD_WPB), (size_t)lds, stream, args);
-  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+// 16-column tiles one workgroup takes per loop iteration, and the loop's
+// workers (waves of the staged body, workgroups of the chunk-register body).
+static inline uint32_t units_per_step(const VariantDesc& d) {
+  return d.body != BODY_CHUNKREG ? (uint32_t)(d.wpb * d.tiles) : (uint32_t)d.tiles;
+}
+static inline uint32_t workers_per_block(const VariantDesc& d) {
+  return d.body != BODY_CHUNKREG ? (uint32_t)d.wpb : 1u;
 }
 
-template <int NP>
-static dg_status launch_fwd_f64(const FwdArgs<double>& p, hipStream_t stream) {
-  if constexpr (f64_staged_ok<NP>()) {
-    if (default_body_f64(NP) == BODY_STAGED)
-      return launch_persistent(fwd_f64_kernel<NP, BODY_STAGED>, p, p.ntiles, DG_FORM_F64, NP, BODY_STAGED,
-                               f64_lds<NP, BODY_STAGED>(), stream);
-  }
-  return launch_persistent(fwd_f64_kernel<NP, BODY_CHUNKREG>, p, p.ntiles, DG_FORM_F64, NP, BODY_CHUNKREG,
-                           f64_lds<NP, BODY_CHUNKREG>(), stream);
-}
-
-template <int NP>
-static dg_status launch_fwd_f32s(const FwdArgs<float>& p, hipStream_t stream) {
-  if (default_body_f32s(NP) == BODY_STAGED)
-    return launch_persistent(fwd_f32s_kernel<NP, BODY_STAGED>, p, p.ntiles, DG_FORM_F32S, NP, BODY_STAGED,
-                             f32s_lds<NP, BODY_STAGED>(), stream);
-  return launch_persistent(fwd_f32s_kernel<NP, BODY_CHUNKREG>, p, p.ntiles, DG_FORM_F32S, NP, BODY_CHUNKREG,
-                           f32s_lds<NP, BODY_CHUNKREG>(), stream);
-}
-
-template <int NP>
-static dg_status launch_adj_f64(const double* D, const double* G, const double* u, const double* gout,
-                                double* gu, double* gG, int64_t K, int32_t F, hipStream_t stream) {
-  const uint32_t E = F <= 16 ? (uint32_t)(16 / F) : 1u;
-  const uint32_t nsub = F <= 16 ? 1u : ceil_div((uint64_t)F, 16);
-  const uint32_t ntiles = ceil_div((uint64_t)K, E);
-  int err = DG_OK;
-  if constexpr (NP >= 84) {
-    // two chunk-register passes: gu, then gG
-    const uint64_t ncols = (uint64_t)K * (uint64_t)F;
-    const uint32_t tiles_a = ceil_div(ncols, 16);
-    auto ka = adjcr_gu_kernel<NP>;
-    const int cap_a = resident_blocks(ka, WAVE * ADJCR_WPB, -1, &err);
-    if (err != DG_OK) return err;
-    hipLaunchKernelGGL(ka, dim3(std::min<uint32_t>(tiles_a, (uint32_t)cap_a)), dim3(WAVE * ADJCR_WPB), 0, stream, D, G,
-                       gout, gu, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP, tiles_a);
-    auto kb = adjcr_gG_kernel<NP>;
-    const int cap_b = resident_blocks(kb, WAVE * ADJCR_WPB, -1, &err);
-    if (err != DG_OK) return err;
-    hipLaunchKernelGGL(kb, dim3(std::min<uint32_t>(ntiles, (uint32_t)cap_b)), dim3(WAVE * ADJCR_WPB), 0, stream, D, u,
-                       gout, gG, (uint32_t)K, (uint32_t)F, (int64_t)ncols * NP, E, nsub, ntiles);
-    return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
-  } else {
-    if (F <= 16) {
-      auto kern = adj_f64_staged_kernel<NP, ADJ_WPB>;
-      const int cap = resident_blocks(kern, WAVE * ADJ_WPB, -1, &err);
-      if (err != DG_OK) return err;
-      const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, ADJ_WPB), (uint32_t)cap);
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * ADJ_WPB), 0, stream, D, G, u, gout, gu, gG, (uint32_t)K,
-                         (uint32_t)F, (int64_t)K * F * NP, E, ntiles);
-    } else {
-      auto kern = adj_f64_kernel<NP, ADJ_WPB>;
-      const int cap = resident_blocks(kern, WAVE * ADJ_WPB, -1, &err);
-      if (err != DG_OK) return err;
-      const uint32_t grid = std::min<uint32_t>(ceil_div(ntiles, ADJ_WPB), (uint32_t)cap);
-      hipLaunchKernelGGL(kern, dim3(grid), dim3(WAVE * ADJ_WPB), 0, stream, D, G, u, gout, gu, gG, (uint32_t)K,
-                         (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
+// The batched kernel of a class.
+static const void* batched_fn(int form, int cls) {
+  if (form == DG_FORM_F64) {
+    switch (cls) {
+      case VCLASS_LIGHT: return reinterpret_cast<const void*>(batched_f64_kernel<VCLASS_LIGHT>);
+      case VCLASS_HEAVY: return reinterpret_cast<const void*>(batched_f64_kernel<VCLASS_HEAVY>);
+      default: return reinterpret_cast<const void*>(batched_f64_kernel<VCLASS_WAVE4>);
     }
-    return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+  }
+  switch (cls) {
+    case VCLASS_LIGHT: return reinterpret_cast<const void*>(batched_f32s_kernel<VCLASS_LIGHT>);
+    case VCLASS_HEAVY: return reinterpret_cast<const void*>(batched_f32s_kernel<VCLASS_HEAVY>);
+    default: return reinterpret_cast<const void*>(batched_f32s_kernel<VCLASS_WAVE4>);
   }
 }
 
-// Partial sums of the D cotangent: a pure function of the problem size, so
-// the result does not depend on the device.
-static uint32_t gd_parts(int64_t K, int32_t Np, int32_t F) {
-  const uint32_t nunits = ceil_div((uint64_t)K * (uint64_t)F, GD_UNIT);
-  return std::min<uint32_t>(nunits, gd_maxpart(Np));
+// Persistent grid of a single-group launch of variant d over `ntiles` tiles.
+static uint32_t single_grid(const VariantDesc& d, uint32_t ntiles, int* err, uint32_t* resident) {
+  const int cap = resident_blocks_fn(d.fn, WAVE * d.wpb, d.lds, err);
+  if (*err != DG_OK) return 0;
+  if (resident) *resident = (uint32_t)cap;
+  return std::min<uint32_t>(ceil_div(ntiles, units_per_step(d)), (uint32_t)cap);
 }
 
-template <int NP>
-static dg_status launch_gd_f64(const double* G, const double* u, const double* gout, double* gD, double* work,
-                               int64_t K, int32_t F, hipStream_t stream) {
-  using S = GdShape<NP>;
-  const uint64_t ncols = (uint64_t)K * (uint64_t)F;
-  const uint32_t npart = gd_parts(K, NP, F);
-  if (npart > 0) {
-    const GdArgs p{G, u, gout, work, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP, ceil_div(ncols, GD_UNIT),
-                   npart};
-    // with NSPLIT > 1 the grid is rounded up to whole groups of 8 ranges (one per XCD)
-    const uint32_t grid = S::NSPLIT == 1 ? npart : ceil_div(npart, 8) * 8 * S::NSPLIT;
-    hipLaunchKernelGGL(gd_partial_kernel<NP>, dim3(grid), dim3(S::NTH), 0, stream, p);
-  }
-  const uint32_t n = 3u * NP * NP;
-  hipLaunchKernelGGL(gd_reduce_kernel, dim3(ceil_div(n, 64)), dim3(64 * GD_RED_PG), 0, stream, work, gD, npart,
-                     n);
+template <typename T>
+static dg_status launch_variant(const VariantDesc& d, const FwdArgs<T>& p, hipStream_t stream) {
+  int err = DG_OK;
+  const uint32_t grid = single_grid(d, p.ntiles, &err, nullptr);
+  if (err != DG_OK) return err;
+  FwdArgs<T> a = p;
+  void* args[] = {&a};
+  if (hipLaunchKernel(d.fn, dim3(grid), dim3(WAVE * d.wpb), args, (size_t)d.lds, stream) != hipSuccess)
+    return DG_ELAUNCH;
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
 
@@ -270,6 +225,107 @@ static double tile_cost_estimate(int form, int Np, uint32_t F) {
     default: eff = form == DG_FORM_F64 ? 0.60 : 0.55; break;  // Np = 120
   }
   return std::max(bytes / bw, flops / peak) / eff;
+}
+
+// Kernels and grids of the adjoint for (NP, K, F): one kernel (staged, or
+// general when F > 16) below Np = 84, two chunk-register passes (gu, then gG)
+// from Np = 84.
+struct AdjPlan {
+  int nk;                // kernels launched
+  const void* fn[2];
+  uint32_t block;
+  uint32_t grid[2];
+  uint32_t resident[2];
+  uint32_t units[2];     // work units of each kernel
+  uint32_t workers[2];   // loop workers per workgroup (waves, or the workgroup itself)
+};
+
+template <int NP>
+static dg_status adj_plan(int64_t K, int32_t F, AdjPlan* pl) {
+  const uint32_t E = F <= 16 ? (uint32_t)(16 / F) : 1u;
+  const uint32_t ntiles = ceil_div((uint64_t)K, E);
+  int err = DG_OK;
+  if constexpr (NP >= 84) {
+    const uint32_t tiles_a = ceil_div((uint64_t)K * (uint64_t)F, 16);
+    pl->nk = 2;
+    pl->block = WAVE * ADJCR_WPB;
+    pl->fn[0] = reinterpret_cast<const void*>(adjcr_gu_kernel<NP>);
+    pl->fn[1] = reinterpret_cast<const void*>(adjcr_gG_kernel<NP>);
+    pl->units[0] = tiles_a;
+    pl->units[1] = ntiles;
+    for (int i = 0; i < 2; ++i) {
+      const int cap = resident_blocks_fn(pl->fn[i], pl->block, -1, &err);
+      if (err != DG_OK) return err;
+      pl->resident[i] = (uint32_t)cap;
+      pl->grid[i] = std::min<uint32_t>(pl->units[i], (uint32_t)cap);
+      pl->workers[i] = 1;
+    }
+  } else {
+    pl->nk = 1;
+    pl->block = WAVE * ADJ_WPB;
+    pl->fn[0] = F <= 16 ? reinterpret_cast<const void*>(adj_f64_staged_kernel<NP, ADJ_WPB>)
+                        : reinterpret_cast<const void*>(adj_f64_kernel<NP, ADJ_WPB>);
+    const int cap = resident_blocks_fn(pl->fn[0], pl->block, -1, &err);
+    if (err != DG_OK) return err;
+    pl->resident[0] = (uint32_t)cap;
+    pl->units[0] = ntiles;
+    pl->grid[0] = std::min<uint32_t>(ceil_div(ntiles, ADJ_WPB), (uint32_t)cap);
+    pl->workers[0] = ADJ_WPB;
+  }
+  return DG_OK;
+}
+
+template <int NP>
+static dg_status launch_adj_f64(const double* D, const double* G, const double* u, const double* gout,
+                                double* gu, double* gG, int64_t K, int32_t F, hipStream_t stream) {
+  const uint32_t E = F <= 16 ? (uint32_t)(16 / F) : 1u;
+  const uint32_t nsub = F <= 16 ? 1u : ceil_div((uint64_t)F, 16);
+  const uint32_t ntiles = ceil_div((uint64_t)K, E);
+  AdjPlan pl;
+  const dg_status st = adj_plan<NP>(K, F, &pl);
+  if (st != DG_OK) return st;
+  if constexpr (NP >= 84) {
+    // two chunk-register passes: gu, then gG
+    const uint64_t ncols = (uint64_t)K * (uint64_t)F;
+    hipLaunchKernelGGL(adjcr_gu_kernel<NP>, dim3(pl.grid[0]), dim3(pl.block), 0, stream, D, G, gout, gu,
+                       (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP, pl.units[0]);
+    hipLaunchKernelGGL(adjcr_gG_kernel<NP>, dim3(pl.grid[1]), dim3(pl.block), 0, stream, D, u, gout, gG, (uint32_t)K,
+                       (uint32_t)F, (int64_t)ncols * NP, E, nsub, ntiles);
+  } else {
+    if (F <= 16)
+      hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D, G, u,
+                         gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, E, ntiles);
+    else
+      hipLaunchKernelGGL((adj_f64_kernel<NP, ADJ_WPB>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D, G, u, gout,
+                         gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
+  }
+  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+}
+
+// Partial sums of the D cotangent: a pure function of the problem size, so
+// the result does not depend on the device.
+static uint32_t gd_parts(int64_t K, int32_t Np, int32_t F) {
+  const uint32_t nunits = ceil_div((uint64_t)K * (uint64_t)F, GD_UNIT);
+  return std::min<uint32_t>(nunits, gd_maxpart(Np));
+}
+
+template <int NP>
+static dg_status launch_gd_f64(const double* G, const double* u, const double* gout, double* gD, double* work,
+                               int64_t K, int32_t F, hipStream_t stream) {
+  using S = GdShape<NP>;
+  const uint64_t ncols = (uint64_t)K * (uint64_t)F;
+  const uint32_t npart = gd_parts(K, NP, F);
+  if (npart > 0) {
+    const GdArgs p{G, u, gout, work, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP, ceil_div(ncols, GD_UNIT),
+                   npart};
+    // with NSPLIT > 1 the grid is rounded up to whole groups of 8 ranges (one per XCD)
+    const uint32_t grid = S::NSPLIT == 1 ? npart : ceil_div(npart, 8) * 8 * S::NSPLIT;
+    hipLaunchKernelGGL(gd_partial_kernel<NP>, dim3(grid), dim3(S::NTH), 0, stream, p);
+  }
+  const uint32_t n = 3u * NP * NP;
+  hipLaunchKernelGGL(gd_reduce_kernel, dim3(ceil_div(n, 64)), dim3(64 * GD_RED_PG), 0, stream, work, gD, npart,
+                     n);
+  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
 
 // ------------------------------------------------------------------ validation
@@ -314,18 +370,17 @@ int32_t dg_supported_np(int32_t Np) {
   }
 }
 
-int32_t dg_body_available(int32_t form, int32_t Np, int32_t body) {
+int32_t dg_variant_count(int32_t form, int32_t Np) {
   if (!dg_supported_np(Np)) return 0;
-  if (form == DG_FORM_F64) return body_ok_f64(Np, body) ? 1 : 0;
-  if (form == DG_FORM_F32S) return body_ok_f32s(Np, body) ? 1 : 0;
-  return 0;
+  return variant_count(form, Np);
 }
 
-int32_t dg_default_body(int32_t form, int32_t Np) {
-  if (!dg_supported_np(Np)) return -1;
-  if (form == DG_FORM_F64) return default_body_f64(Np);
-  if (form == DG_FORM_F32S) return default_body_f32s(Np);
-  return -1;
+dg_status dg_variant_query(int32_t form, int32_t Np, int32_t variant, dg_variant_info* info) {
+  if (!info) return DG_EINVAL;
+  VariantDesc d;
+  if (!dg_supported_np(Np) || !variant_desc(form, Np, variant, &d)) return DG_EUNSUPPORTED;
+  *info = dg_variant_info{d.body, d.wpb, d.tiles, d.cls, d.lds};
+  return DG_OK;
 }
 
 #define DGVOL_DISPATCH(LAUNCH, ...)            \
@@ -340,28 +395,39 @@ int32_t dg_default_body(int32_t form, int32_t Np) {
   }                                            \
   return DG_EUNSUPPORTED;
 
-dg_status dg_volume(const double* D, const double* G, const double* u, double* out, int64_t K, int32_t Np,
-                    int32_t F, void* stream) {
+dg_status dg_volume_variant(int32_t form, int32_t variant, const void* D, const void* G, const void* u, void* out,
+                            int64_t K, int32_t Np, int32_t F, void* stream) {
   bool noop = false;
   const dg_status st = check_common(K, Np, F, &noop);
-  if (st != DG_OK || noop) return st;
+  if (st != DG_OK) return st;
+  if (form != DG_FORM_F64 && form != DG_FORM_F32S) return DG_EUNSUPPORTED;
+  VariantDesc d;
+  if (!variant_desc(form, Np, variant == DG_VARIANT_AUTO ? 0 : variant, &d)) return DG_EUNSUPPORTED;
+  if (noop) return DG_OK;
+  const uintptr_t word = form == DG_FORM_F64 ? 8 : 4;
   if (!D || !G || !u || !out) return DG_EINVAL;
-  if (!aligned(D, 8) || !aligned(G, 8) || !aligned(u, 8) || !aligned(out, 8)) return DG_EINVAL;
+  if (!aligned(D, word) || !aligned(G, word) || !aligned(u, word) || !aligned(out, word)) return DG_EINVAL;
   const uint64_t ncols = (uint64_t)K * (uint64_t)F;
-  const FwdArgs<double> p{D, G, u, out, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * Np, ceil_div(ncols, 16)};
-  DGVOL_DISPATCH(launch_fwd_f64, p, (hipStream_t)stream)
+  if (form == DG_FORM_F64) {
+    const FwdArgs<double> p{static_cast<const double*>(D), static_cast<const double*>(G),
+                            static_cast<const double*>(u), static_cast<double*>(out), (uint32_t)ncols, (uint32_t)F,
+                            (int64_t)ncols * Np, ceil_div(ncols, 16)};
+    return launch_variant(d, p, (hipStream_t)stream);
+  }
+  const FwdArgs<float> p{static_cast<const float*>(D), static_cast<const float*>(G), static_cast<const float*>(u),
+                         static_cast<float*>(out), (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * Np,
+                         ceil_div(ncols, 16)};
+  return launch_variant(d, p, (hipStream_t)stream);
+}
+
+dg_status dg_volume(const double* D, const double* G, const double* u, double* out, int64_t K, int32_t Np,
+                    int32_t F, void* stream) {
+  return dg_volume_variant(DG_FORM_F64, DG_VARIANT_AUTO, D, G, u, out, K, Np, F, stream);
 }
 
 dg_status dg_volume_f32s(const float* D, const float* G, const float* u, float* out, int64_t K, int32_t Np,
                          int32_t F, void* stream) {
-  bool noop = false;
-  const dg_status st = check_common(K, Np, F, &noop);
-  if (st != DG_OK || noop) return st;
-  if (!D || !G || !u || !out) return DG_EINVAL;
-  if (!aligned(D, 4) || !aligned(G, 4) || !aligned(u, 4) || !aligned(out, 4)) return DG_EINVAL;
-  const uint64_t ncols = (uint64_t)K * (uint64_t)F;
-  const FwdArgs<float> p{D, G, u, out, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * Np, ceil_div(ncols, 16)};
-  DGVOL_DISPATCH(launch_fwd_f32s, p, (hipStream_t)stream)
+  return dg_volume_variant(DG_FORM_F32S, DG_VARIANT_AUTO, D, G, u, out, K, Np, F, stream);
 }
 
 dg_status dg_volume_adjoint(const double* D, const double* G, const double* u, const double* gout, double* gu,
@@ -408,89 +474,171 @@ dg_status dg_volume_batched(const dg_group* groups, int32_t ngroups, int32_t F, 
   if (form != DG_FORM_F64 && form != DG_FORM_F32S) return DG_EUNSUPPORTED;
   if (ngroups > 0 && !groups) return DG_EINVAL;
   const uintptr_t word = form == DG_FORM_F64 ? 8 : 4;
-  BatchArgs a{};
-  a.F = (uint32_t)F;
-  double cost[DG_MAX_GROUPS];
-  uint32_t max_blocks[DG_MAX_GROUPS];
-  double total_cost = 0.0;
-  int lds = 0;
-  int ng = 0;
+  // validate everything first (nothing is launched on error), then one launch per class
+  VariantDesc desc[DG_MAX_GROUPS];
+  bool live[DG_MAX_GROUPS];
   for (int i = 0; i < ngroups; ++i) {
     const dg_group& gr = groups[i];
     bool noop = false;
     const dg_status st = check_common(gr.K, gr.Np, F, &noop);
     if (st != DG_OK) return st;
-    if (gr.body != DG_BODY_AUTO && !dg_body_available(form, gr.Np, gr.body)) return DG_EUNSUPPORTED;
+    if (!variant_desc(form, gr.Np, gr.variant == DG_VARIANT_AUTO ? 0 : gr.variant, &desc[i]))
+      return DG_EUNSUPPORTED;
+    live[i] = !noop;
     if (noop) continue;
     if (!gr.D || !gr.G || !gr.u || !gr.out) return DG_EINVAL;
     if (!aligned(gr.D, word) || !aligned(gr.G, word) || !aligned(gr.u, word) || !aligned(gr.out, word))
       return DG_EINVAL;
-    const int body = gr.body != DG_BODY_AUTO
-                         ? gr.body
-                         : (form == DG_FORM_F64 ? default_body_f64(gr.Np) : default_body_f32s(gr.Np));
-    const uint64_t ncols = (uint64_t)gr.K * (uint64_t)F;
-    GroupDev& gd = a.g[ng];
-    gd.Np = gr.Np;
-    gd.body = body;
-    gd.ncols = (uint32_t)ncols;
-    gd.ntiles = ceil_div(ncols, 16);
-    gd.plane = (int64_t)ncols * gr.Np;
-    gd.D = gr.D;
-    gd.G = gr.G;
-    gd.u = gr.u;
-    gd.out = gr.out;
-    const double per_tile = gr.cost > 0.0 ? gr.cost : tile_cost_estimate(form, gr.Np, (uint32_t)F);
-    cost[ng] = per_tile * gd.ntiles;
-    max_blocks[ng] = ceil_div(gd.ntiles, tiles_per_block(form, gr.Np, body));
-    total_cost += cost[ng];
-    lds = std::max(lds, lds_bytes(form, gr.Np, body));
-    ++ng;
   }
-  if (ng == 0) return DG_OK;
-  a.ngroups = ng;
+  for (int cls = 0; cls < NUM_VCLASSES; ++cls) {
+    BatchArgs a{};
+    a.F = (uint32_t)F;
+    double cost[DG_MAX_GROUPS];
+    uint32_t max_blocks[DG_MAX_GROUPS];
+    double total_cost = 0.0;
+    int lds = 0;
+    int ng = 0;
+    for (int i = 0; i < ngroups; ++i) {
+      if (!live[i] || desc[i].cls != cls) continue;
+      const dg_group& gr = groups[i];
+      const uint64_t ncols = (uint64_t)gr.K * (uint64_t)F;
+      GroupDev& gd = a.g[ng];
+      gd.Np = gr.Np;
+      gd.variant = gr.variant == DG_VARIANT_AUTO ? 0 : gr.variant;
+      gd.ncols = (uint32_t)ncols;
+      gd.ntiles = ceil_div(ncols, 16);
+      gd.plane = (int64_t)ncols * gr.Np;
+      gd.D = gr.D;
+      gd.G = gr.G;
+      gd.u = gr.u;
+      gd.out = gr.out;
+      const double per_tile = gr.cost > 0.0 ? gr.cost : tile_cost_estimate(form, gr.Np, (uint32_t)F);
+      cost[ng] = per_tile * gd.ntiles;
+      max_blocks[ng] = ceil_div(gd.ntiles, units_per_step(desc[i]));
+      total_cost += cost[ng];
+      lds = std::max(lds, desc[i].lds);
+      ++ng;
+    }
+    if (ng == 0) continue;
+    a.ngroups = ng;
+    int err = DG_OK;
+    const void* fn = batched_fn(form, cls);
+    const int block = WAVE * class_waves(cls);
+    const int cap = resident_blocks_fn(fn, block, lds, &err);
+    if (err != DG_OK) return err;
+    // Split the resident workgroups so that the largest cost per workgroup is as
+    // small as possible (Jefferson / D'Hondt apportionment): every group gets the
+    // whole part of its proportional share, at least one and at most what it can
+    // use, then each workgroup left goes to the group with the largest cost per
+    // workgroup.  Plain rounding of the shares can leave a small group one
+    // workgroup short, and that group then finishes last.
+    uint32_t nb[DG_MAX_GROUPS];
+    uint32_t used = 0;
+    for (int i = 0; i < ng; ++i) {
+      const uint32_t share = (uint32_t)((double)cap * cost[i] / total_cost);
+      nb[i] = std::max<uint32_t>(1u, std::min(share, max_blocks[i]));
+      used += nb[i];
+    }
+    while (used < (uint32_t)cap) {
+      int pick = -1;
+      for (int i = 0; i < ng; ++i)
+        if (nb[i] < max_blocks[i] && (pick < 0 || cost[i] * nb[pick] > cost[pick] * nb[i])) pick = i;
+      if (pick < 0) break;
+      ++nb[pick];
+      ++used;
+    }
+    uint32_t begin = 0;
+    for (int i = 0; i < ng; ++i) {
+      a.wg_begin[i] = begin;
+      begin += nb[i];
+    }
+    for (int i = ng; i <= MAX_GROUPS; ++i) a.wg_begin[i] = begin;
+    void* args[] = {&a};
+    if (hipLaunchKernel(fn, dim3(begin), dim3(block), args, (size_t)lds, (hipStream_t)stream) != hipSuccess)
+      return DG_ELAUNCH;
+    if (hipGetLastError() != hipSuccess) return DG_ELAUNCH;
+  }
+  return DG_OK;
+}
+
+dg_status dg_launch_shape_query(int32_t op, int32_t form, int32_t Np, int32_t variant, int64_t K, int32_t F,
+                                dg_launch_shape* shape) {
+  if (!shape || K < 1 || F < 1) return DG_EINVAL;
+  if (!dg_supported_np(Np)) return DG_EUNSUPPORTED;
+  if ((uint64_t)K * (uint64_t)F > (uint64_t)INT32_MAX) return DG_EINVAL;
   int err = DG_OK;
-  const int cap = form == DG_FORM_F64 ? resident_blocks(batched_f64_kernel, WAVE * FWD_WPB, lds, &err)
-                                      : resident_blocks(batched_f32s_kernel, WAVE * FWD_WPB, lds, &err);
-  if (err != DG_OK) return err;
-  // Split the resident workgroups so that the largest cost per workgroup is as
-  // small as possible (Jefferson / D'Hondt apportionment): every group gets the
-  // whole part of its proportional share, at least one and at most what it can
-  // use, then each workgroup left goes to the group with the largest cost per
-  // workgroup.  Plain rounding of the shares can leave a small group one
-  // workgroup short, and that group then finishes last.
-  uint32_t nb[DG_MAX_GROUPS];
-  uint32_t used = 0;
-  for (int i = 0; i < ng; ++i) {
-    const uint32_t share = (uint32_t)((double)cap * cost[i] / total_cost);
-    nb[i] = std::max<uint32_t>(1u, std::min(share, max_blocks[i]));
-    used += nb[i];
+  dg_launch_shape sh{};
+  if (op == DG_OP_FORWARD || op == DG_OP_BATCHED) {
+    VariantDesc d;
+    if (!variant_desc(form, Np, variant == DG_VARIANT_AUTO ? 0 : variant, &d)) return DG_EUNSUPPORTED;
+    const uint32_t ntiles = ceil_div((uint64_t)K * (uint64_t)F, 16);
+    const uint32_t per = units_per_step(d);
+    uint32_t cap = 0;
+    if (op == DG_OP_FORWARD) {
+      cap = (uint32_t)resident_blocks_fn(d.fn, WAVE * d.wpb, d.lds, &err);
+      sh.block = WAVE * d.wpb;
+    } else {
+      sh.block = WAVE * class_waves(d.cls);
+      cap = (uint32_t)resident_blocks_fn(batched_fn(form, d.cls), sh.block, d.lds, &err);
+    }
+    if (err != DG_OK) return err;
+    sh.grid = std::min<uint32_t>(ceil_div(ntiles, per), cap);
+    sh.lds_bytes = (uint32_t)d.lds;
+    sh.resident = cap;
+    sh.units = ntiles;
+    sh.units_per_step = per;
+    // the loop hands out runs of `tiles` tiles to grid x workers workers in turn
+    const uint32_t runs = ceil_div(ntiles, (uint32_t)d.tiles);
+    const uint32_t workers = sh.grid * workers_per_block(d);
+    sh.min_iters = runs / workers;
+    sh.max_iters = ceil_div(runs, workers);
+  } else if (op == DG_OP_ADJOINT) {
+    if (form != DG_FORM_F64) return DG_EUNSUPPORTED;
+    AdjPlan pl;
+    dg_status st = DG_EUNSUPPORTED;
+    switch (Np) {
+      case 4: st = adj_plan<4>(K, F, &pl); break;
+      case 10: st = adj_plan<10>(K, F, &pl); break;
+      case 20: st = adj_plan<20>(K, F, &pl); break;
+      case 35: st = adj_plan<35>(K, F, &pl); break;
+      case 56: st = adj_plan<56>(K, F, &pl); break;
+      case 84: st = adj_plan<84>(K, F, &pl); break;
+      case 120: st = adj_plan<120>(K, F, &pl); break;
+    }
+    if (st != DG_OK) return st;
+    sh.grid = pl.grid[0];
+    sh.block = pl.block;
+    sh.lds_bytes = 0;
+    sh.resident = pl.resident[0];
+    sh.units = pl.units[0];
+    sh.units_per_step = pl.workers[0];
+    sh.min_iters = UINT32_MAX;
+    sh.max_iters = 0;
+    for (int i = 0; i < pl.nk; ++i) {
+      const uint32_t workers = pl.grid[i] * pl.workers[i];
+      sh.min_iters = std::min(sh.min_iters, pl.units[i] / workers);
+      sh.max_iters = std::max(sh.max_iters, ceil_div(pl.units[i], workers));
+    }
+  } else {
+    return DG_EINVAL;
   }
-  while (used < (uint32_t)cap) {
-    int pick = -1;
-    for (int i = 0; i < ng; ++i)
-      if (nb[i] < max_blocks[i] && (pick < 0 || cost[i] * nb[pick] > cost[pick] * nb[i])) pick = i;
-    if (pick < 0) break;
-    ++nb[pick];
-    ++used;
-  }
-  uint32_t begin = 0;
-  for (int i = 0; i < ng; ++i) {
-    a.wg_begin[i] = begin;
-    begin += nb[i];
-  }
-  for (int i = ng; i <= MAX_GROUPS; ++i) a.wg_begin[i] = begin;
-  if (form == DG_FORM_F64)
-    hipLaunchKernelGGL(batched_f64_kernel, dim3(begin), dim3(WAVE * FWD_WPB), (size_t)lds, (hipStream_t)stream, a);
-  else
-    hipLaunchKernelGGL(batched_f32s_kernel, dim3(begin), dim3(WAVE * FWD_WPB), (size_t)lds, (hipStream_t)stream,
-                       a);
-  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+  *shape = sh;
+  return DG_OK;
 }
 
 dg_status dg_stream_calibrate(const double* src, double* dst, int64_t n, int32_t copies, void* stream) {
   if (n < 0 || copies < 1 || copies > 3) return DG_EINVAL;
   if (n == 0) return DG_OK;
   if (!src || !dst || !aligned(src, 8) || !aligned(dst, 8)) return DG_EINVAL;
+  if (aligned(src, 16) && aligned(dst, 16) && n % 2 == 0) {
+    const int64_t n2 = n / 2;
+    const int64_t per_block = (int64_t)STREAM_BLOCK * STREAM_U;
+    const int64_t grid = (n2 + per_block - 1) / per_block;
+    if (grid > INT32_MAX) return DG_EINVAL;
+    hipLaunchKernelGGL(stream16_kernel, dim3((uint32_t)grid), dim3(STREAM_BLOCK), 0, (hipStream_t)stream,
+                       reinterpret_cast<const f64x2*>(src), reinterpret_cast<f64x2*>(dst), n2, copies);
+    return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+  }
   int err = DG_OK;
   const int dev = current_device(&err);
   if (dev < 0) return err;

@@ -2,7 +2,7 @@
 
 The functions named like the C entry points (``dg_volume``,
 ``dg_volume_adjoint``, ``dg_volume_grad_d``, ``dg_volume_f32s``,
-``dg_volume_batched`` and the two calibration calls) take torch tensors on the
+``dg_volume_variant``, ``dg_volume_batched`` and the two calibration calls) take torch tensors on the
 GPU, check dtype/device/shape/contiguity, and pass raw device pointers plus
 torch's current HIP stream to the library.  Every arithmetic step runs in the
 HIP kernels; there is no CPU or PyTorch fallback: if the library is missing or
@@ -31,17 +31,34 @@ SUPPORTED_NP = (4, 10, 20, 35, 56, 84, 120)
 
 FORM_F64 = 0
 FORM_F32S = 1
-BODY_AUTO = -1
 BODY_STAGED = 0
 BODY_CHUNKREG = 1
+BODY_STAGED_LEAN = 2
+VARIANT_AUTO = -1
 MAX_GROUPS = 16
+
+OP_FORWARD = 0
+OP_BATCHED = 1
+OP_ADJOINT = 2
 
 
 class DgGroup(ctypes.Structure):
     """Mirror of `dg_group` in dgvol.h."""
-    _fields_ = [("Np", ctypes.c_int32), ("body", ctypes.c_int32), ("K", ctypes.c_int64),
+    _fields_ = [("Np", ctypes.c_int32), ("variant", ctypes.c_int32), ("K", ctypes.c_int64),
                 ("D", ctypes.c_void_p), ("G", ctypes.c_void_p), ("u", ctypes.c_void_p),
                 ("out", ctypes.c_void_p), ("cost", ctypes.c_double)]
+
+
+class DgVariantInfo(ctypes.Structure):
+    """Mirror of `dg_variant_info` in dgvol.h."""
+    _fields_ = [("body", ctypes.c_int32), ("waves", ctypes.c_int32), ("tiles", ctypes.c_int32),
+                ("batch_class", ctypes.c_int32), ("lds_bytes", ctypes.c_int32)]
+
+
+class DgLaunchShape(ctypes.Structure):
+    """Mirror of `dg_launch_shape` in dgvol.h."""
+    _fields_ = [(name, ctypes.c_uint32) for name in
+                ("grid", "block", "lds_bytes", "resident", "units", "units_per_step", "min_iters", "max_iters")]
 
 _lib = None
 
@@ -86,10 +103,14 @@ def load_library(path=None):
     lib.dg_mfma_calibrate.restype = I32
     lib.dg_volume_batched.argtypes = [ctypes.POINTER(DgGroup), I32, I32, I32, P]
     lib.dg_volume_batched.restype = I32
-    lib.dg_body_available.argtypes = [I32, I32, I32]
-    lib.dg_body_available.restype = I32
-    lib.dg_default_body.argtypes = [I32, I32]
-    lib.dg_default_body.restype = I32
+    lib.dg_variant_count.argtypes = [I32, I32]
+    lib.dg_variant_count.restype = I32
+    lib.dg_variant_query.argtypes = [I32, I32, I32, ctypes.POINTER(DgVariantInfo)]
+    lib.dg_variant_query.restype = I32
+    lib.dg_volume_variant.argtypes = [I32, I32, P, P, P, P, I64, I32, I32, P]
+    lib.dg_volume_variant.restype = I32
+    lib.dg_launch_shape_query.argtypes = [I32, I32, I32, I32, I64, I32, ctypes.POINTER(DgLaunchShape)]
+    lib.dg_launch_shape_query.restype = I32
     if path is None:
         _lib = lib
     return lib
@@ -221,13 +242,54 @@ def dg_volume_f32s(D, G, u, out=None):
     return out
 
 
-def dg_volume_batched(groups, form=FORM_F64, outs=None, bodies=None, costs=None):
-    """Forward derivative of several element groups (possibly different orders) in one launch.
+def dg_volume_variant(form, variant, D, G, u, out=None):
+    """Forward product of one group with an explicit launch variant (VARIANT_AUTO or an index
+    below variant_count(form, Np)); float64 tensors for FORM_F64, float32 for FORM_F32S."""
+    K, F, Np = _sizes(u)
+    dev = u.device
+    dtype = torch.float64 if form == FORM_F64 else torch.float32
+    _check_tensor("u", u, dtype, (K, F, Np))
+    _check_tensor("D", D, dtype, (3, Np, Np), dev)
+    _check_tensor("G", G, dtype, (K, 9), dev)
+    if out is None:
+        out = torch.empty((3, K, F, Np), dtype=dtype, device=dev)
+    _check_tensor("out", out, dtype, (3, K, F, Np), dev)
+    with torch.cuda.device(dev):
+        st = load_library().dg_volume_variant(int(form), int(variant), D.data_ptr(), G.data_ptr(), u.data_ptr(),
+                                              out.data_ptr(), K, Np, F, _stream_handle(dev))
+    _raise_on(st, "dg_volume_variant")
+    return out
+
+
+def variant_count(form, Np):
+    """Number of compiled launch variants of the forward product for (form, Np)."""
+    return int(load_library().dg_variant_count(int(form), int(Np)))
+
+
+def variant_info(form, Np, variant):
+    """dict(body, waves, tiles, batch_class, lds_bytes) of one variant (host query)."""
+    info = DgVariantInfo()
+    _raise_on(load_library().dg_variant_query(int(form), int(Np), int(variant), ctypes.byref(info)),
+              "dg_variant_query")
+    return {f: int(getattr(info, f)) for f, _ in DgVariantInfo._fields_}
+
+
+def launch_shape(op, form, Np, variant, K, F):
+    """Grid, occupancy and loop iterations an operation would use on the current device."""
+    sh = DgLaunchShape()
+    _raise_on(load_library().dg_launch_shape_query(int(op), int(form), int(Np), int(variant), int(K), int(F),
+                                                   ctypes.byref(sh)), "dg_launch_shape_query")
+    return {f: int(getattr(sh, f)) for f, _ in DgLaunchShape._fields_}
+
+
+def dg_volume_batched(groups, form=FORM_F64, outs=None, variants=None, costs=None):
+    """Forward derivative of several element groups (possibly different orders), one persistent
+    launch per variant class.
 
     groups: sequence of (D, G, u) tensor triples sharing F and the form's dtype
     (float64 for FORM_F64, float32 for FORM_F32S).  outs: optional matching
-    output tensors (3, K, F, Np).  bodies: optional per-group body ids
-    (BODY_AUTO, BODY_STAGED, BODY_CHUNKREG).  costs: optional measured cost of
+    output tensors (3, K, F, Np).  variants: optional per-group variant index
+    (VARIANT_AUTO or below variant_count).  costs: optional measured cost of
     one 16-column tile per group (sets the split of workgroups).  Returns outs.
     """
     if len(groups) > MAX_GROUPS:
@@ -250,7 +312,7 @@ def dg_volume_batched(groups, form=FORM_F64, outs=None, bodies=None, costs=None)
         _check_tensor("out", out, dtype, (3, K, F, Np), dev)
         res.append(out)
         arr[gi].Np = Np
-        arr[gi].body = BODY_AUTO if bodies is None else int(bodies[gi])
+        arr[gi].variant = VARIANT_AUTO if variants is None else int(variants[gi])
         arr[gi].K = K
         arr[gi].D, arr[gi].G, arr[gi].u, arr[gi].out = D.data_ptr(), G.data_ptr(), u.data_ptr(), out.data_ptr()
         arr[gi].cost = 0.0 if costs is None else float(costs[gi])
@@ -258,14 +320,6 @@ def dg_volume_batched(groups, form=FORM_F64, outs=None, bodies=None, costs=None)
         st = load_library().dg_volume_batched(arr, len(groups), int(F), int(form), _stream_handle(dev))
     _raise_on(st, "dg_volume_batched")
     return res
-
-
-def body_available(form, Np, body):
-    return bool(load_library().dg_body_available(int(form), int(Np), int(body)))
-
-
-def default_body(form, Np):
-    return int(load_library().dg_default_body(int(form), int(Np)))
 
 
 def dg_stream_calibrate(src, dst, copies):

@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_version_and_strerror(lib):
-    assert lib.dg_abi_version() == 1
+    assert lib.dg_abi_version() == 2
     for st in (0, -1, -2, -3, -4, -99):
         msg = lib.dg_strerror(st)
         assert isinstance(msg, bytes) and msg
@@ -161,7 +161,7 @@ def test_library_geometric_factors():
 def _groups(n, **kw):
     arr = (dgvol.DgGroup * max(n, 1))()
     for i in range(n):
-        arr[i].Np, arr[i].body, arr[i].K = kw.get("Np", 35), kw.get("body", -1), kw.get("K", 10)
+        arr[i].Np, arr[i].variant, arr[i].K = kw.get("Np", 35), kw.get("variant", -1), kw.get("K", 10)
         arr[i].D = arr[i].G = arr[i].u = arr[i].out = kw.get("ptr", FAKE)
         arr[i].cost = 0.0
     return arr
@@ -180,23 +180,77 @@ def test_batched_validation(lib):
     assert f(_groups(2, K=-1), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL
     assert f(_groups(2, ptr=None), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL
     assert f(_groups(2, ptr=FAKE + 4), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL  # misaligned double
-    assert f(_groups(2, body=5), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EUNSUPPORTED
-    # the staged FP64 body needs D in LDS: not available for the two largest orders
-    assert f(_groups(1, Np=120, body=0, K=0), 1, 3, dgvol.FORM_F64, None) == dgvol.DG_EUNSUPPORTED
+    assert f(_groups(2, variant=15), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EUNSUPPORTED
+    assert f(_groups(2, variant=-2), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EUNSUPPORTED
+    # order 7 (Np = 120) has one FP64 variant: index 1 is refused even for an empty group
+    assert f(_groups(1, Np=120, variant=1, K=0), 1, 3, dgvol.FORM_F64, None) == dgvol.DG_EUNSUPPORTED
     assert f(None, 1, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL
 
 
-def test_bodies(lib):
-    for Np in (4, 10, 20, 35, 56, 84, 120):
-        assert lib.dg_body_available(dgvol.FORM_F64, Np, dgvol.BODY_CHUNKREG) == 1
-        assert lib.dg_body_available(dgvol.FORM_F32S, Np, dgvol.BODY_STAGED) == 1
-        assert lib.dg_body_available(dgvol.FORM_F32S, Np, dgvol.BODY_CHUNKREG) == 1
-        for form in (dgvol.FORM_F64, dgvol.FORM_F32S):
-            d = lib.dg_default_body(form, Np)
-            assert d in (0, 1) and lib.dg_body_available(form, Np, d) == 1
-    assert [lib.dg_body_available(dgvol.FORM_F64, n, dgvol.BODY_STAGED) for n in (35, 56, 84, 120)] == [1, 1, 0, 0]
-    assert lib.dg_default_body(dgvol.FORM_F64, 36) == -1
-    assert lib.dg_body_available(5, 35, 0) == 0
+def test_variant_tables(lib):
+    """Every (form, Np) has variants; variant 0 is the default; the staged FP64 body, which keeps
+    D in LDS, is not offered where D does not fit (Np = 84, 120); every variant fits the LDS of a
+    CU and its class matches its workgroup size."""
+    seen_bodies = set()
+    for form in (dgvol.FORM_F64, dgvol.FORM_F32S):
+        for Np in (4, 10, 20, 35, 56, 84, 120):
+            n = lib.dg_variant_count(form, Np)
+            assert 1 <= n <= 16
+            shapes = set()
+            for v in range(n):
+                info = dgvol.variant_info(form, Np, v)
+                assert info["body"] in (dgvol.BODY_STAGED, dgvol.BODY_CHUNKREG, dgvol.BODY_STAGED_LEAN)
+                if info["body"] == dgvol.BODY_STAGED_LEAN:  # held to two 8-wave workgroups per CU
+                    assert form == dgvol.FORM_F64 and info["waves"] == 8 and info["batch_class"] == 0
+                assert info["waves"] in (4, 8) and info["tiles"] in (1, 2, 4, 8)
+                assert 0 < info["lds_bytes"] <= 160 * 1024
+                assert (info["batch_class"] == 2) == (info["waves"] == 4)
+                if form == dgvol.FORM_F64 and Np >= 84:
+                    assert info["body"] == dgvol.BODY_CHUNKREG
+                if info["batch_class"] == 0:  # LIGHT: two 8-wave workgroups must fit the LDS of a CU
+                    assert 2 * info["lds_bytes"] <= 160 * 1024
+                key = (info["body"], info["waves"], info["tiles"])
+                assert key not in shapes, f"duplicate variant {key} for form {form} Np {Np}"
+                shapes.add(key)
+                seen_bodies.add((form, info["body"]))
+            info = dgvol.DgVariantInfo()
+            assert lib.dg_variant_query(form, Np, n, ctypes.byref(info)) == dgvol.DG_EUNSUPPORTED
+            assert lib.dg_variant_query(form, Np, -1, ctypes.byref(info)) == dgvol.DG_EUNSUPPORTED
+            assert lib.dg_variant_query(form, Np, 0, None) == dgvol.DG_EINVAL
+    assert len(seen_bodies) == 5
+    assert lib.dg_variant_count(dgvol.FORM_F64, 36) == 0
+    assert lib.dg_variant_count(5, 35) == 0
+    # the defaults the single-group entry points use
+    assert dgvol.variant_info(dgvol.FORM_F64, 35, 0)["body"] == dgvol.BODY_STAGED
+    assert dgvol.variant_info(dgvol.FORM_F64, 120, 0)["body"] == dgvol.BODY_CHUNKREG
+
+
+def test_variant_entry_validation(lib):
+    f = lib.dg_volume_variant
+    F64, F32 = dgvol.FORM_F64, dgvol.FORM_F32S
+    assert f(F64, -1, FAKE, FAKE, FAKE, FAKE, 0, 35, 5, None) == dgvol.DG_OK
+    assert f(F64, 1, FAKE, FAKE, FAKE, FAKE, 0, 35, 5, None) == dgvol.DG_OK
+    assert f(F64, 9, FAKE, FAKE, FAKE, FAKE, 0, 35, 5, None) == dgvol.DG_EUNSUPPORTED
+    assert f(F64, -2, FAKE, FAKE, FAKE, FAKE, 10, 35, 5, None) == dgvol.DG_EUNSUPPORTED
+    assert f(3, 0, FAKE, FAKE, FAKE, FAKE, 10, 35, 5, None) == dgvol.DG_EUNSUPPORTED
+    assert f(F64, 0, FAKE, FAKE, FAKE, FAKE, 10, 36, 5, None) == dgvol.DG_EUNSUPPORTED
+    assert f(F64, 0, FAKE, FAKE, FAKE, FAKE, -1, 35, 5, None) == dgvol.DG_EINVAL
+    for i in range(4):
+        ptrs = [FAKE] * 4
+        ptrs[i] = None
+        assert f(F32, 0, *ptrs, 10, 35, 5, None) == dgvol.DG_EINVAL
+        ptrs[i] = FAKE + 4  # fine for float, misaligned for double
+        assert f(F64, 0, *ptrs, 10, 35, 5, None) == dgvol.DG_EINVAL
+        ptrs[i] = FAKE + 2
+        assert f(F32, 0, *ptrs, 10, 35, 5, None) == dgvol.DG_EINVAL
+    sh = dgvol.DgLaunchShape()
+    q = lib.dg_launch_shape_query
+    assert q(dgvol.OP_FORWARD, F64, 35, 0, 10, 5, None) == dgvol.DG_EINVAL
+    assert q(dgvol.OP_FORWARD, F64, 35, 0, 0, 5, ctypes.byref(sh)) == dgvol.DG_EINVAL
+    assert q(dgvol.OP_FORWARD, F64, 35, 0, 10, 0, ctypes.byref(sh)) == dgvol.DG_EINVAL
+    assert q(7, F64, 35, 0, 10, 5, ctypes.byref(sh)) == dgvol.DG_EINVAL
+    assert q(dgvol.OP_FORWARD, F64, 36, 0, 10, 5, ctypes.byref(sh)) == dgvol.DG_EUNSUPPORTED
+    assert q(dgvol.OP_FORWARD, F64, 35, 12, 10, 5, ctypes.byref(sh)) == dgvol.DG_EUNSUPPORTED
 
 
 def test_autotune_cache_io(tmp_path, monkeypatch):
@@ -209,9 +263,12 @@ def test_autotune_cache_io(tmp_path, monkeypatch):
     assert autotune.load_cache() == {}
     p.write_text("[1, 2]")
     assert autotune.load_cache() == {}
-    autotune.save_cache({"gfx950/abi1": {"f64/Np35/F3": {"body": 0, "tile_cost_s": 1e-7}}})
-    assert autotune.load_cache()["gfx950/abi1"]["f64/Np35/F3"]["body"] == 0
-    assert autotune._valid_entry({"body": 1, "tile_cost_s": 2e-7})
-    assert not autotune._valid_entry({"body": 1, "tile_cost_s": -1})
-    assert not autotune._valid_entry({"body": "x", "tile_cost_s": 1})
+    autotune.save_cache({"gfx950/abi2": {"f64/Np35/F3": {"variant": 0, "tile_cost_s": 1e-7}}})
+    assert autotune.load_cache()["gfx950/abi2"]["f64/Np35/F3"]["variant"] == 0
+    ok = {"variant": 1, "single_variant": 0, "tile_cost_s": 2e-7}
+    assert autotune._valid_entry(ok, dgvol.FORM_F64, 35)
+    assert not autotune._valid_entry(dict(ok, tile_cost_s=-1), dgvol.FORM_F64, 35)
+    assert not autotune._valid_entry(dict(ok, variant="x"), dgvol.FORM_F64, 35)
+    assert not autotune._valid_entry(dict(ok, variant=1), dgvol.FORM_F64, 120)  # order 7 has one FP64 variant
+    assert not autotune._valid_entry(dict(ok, single_variant=99), dgvol.FORM_F64, 35)
     assert autotune.entry_key(1, 120, 3) == "f32s/Np120/F3"

@@ -120,23 +120,6 @@ def test_forward_on_side_stream():
     check_planes(host(out), oracle.volume(D, G, u), forward_cond(D, G, u))
 
 
-def test_forward_workload2_full_size_sampled():
-    """Order 4, K=2^20, F=5, u ~ N(0,1) (the benchmark workload and launch), 4096 sampled elements."""
-    N, K, F = 4, 1 << 20, 5
-    _say(f"forward workload2 N={N} K={K} F={F}")
-    D = oracle.derivative_matrices(N)
-    G = oracle.geometric_factors(synth.tet_vertices(K, synth.mesh_seed(2)))
-    u = synth.fields(K, F, 35, synth.field_seed(2), "normal")
-    Dd, Gd, ud = dev(D), dev(G), dev(u)
-    out = dgvol.dg_volume(Dd, Gd, ud)
-    idx = np.sort(np.random.default_rng(2).choice(K, 4096, replace=False))
-    idx = np.unique(np.concatenate([idx, [0, 1, K - 2, K - 1]]))
-    got = host(out[:, torch.from_numpy(idx).cuda()])
-    ref = oracle.volume(D, G[idx], u[idx])
-    check_planes(got, ref, forward_cond(D, G[idx], u[idx]))
-    assert np.isfinite(host(out.view(-1)[:: 997])).all()
-
-
 # ------------------------------------------------------------------ adjoint FP64
 
 def _check_adjoint(D, G, u, gout, gu, gG):
@@ -507,19 +490,20 @@ def test_batched_matches_single_and_oracle(form):
 
 
 @pytest.mark.parametrize("form", [dgvol.FORM_F64, dgvol.FORM_F32S])
-def test_batched_every_body(form):
-    """Every available body of every order gives the oracle's result (and equal results across
-    bodies up to the parity bar)."""
-    sizes = {N: 97 for N in range(1, 8)}
+def test_batched_every_variant_one_launch(form):
+    """Every variant of every order in one batch (one launch per variant class, the groups of
+    a class sharing its workgroups) gives the oracle's result."""
     F = 2
-    _say(f"batched bodies form={form}")
-    D, G, u = _mixed_case(sizes, F, form, 4100)
+    _say(f"batched variants form={form}")
     cast = (lambda x: x) if form == dgvol.FORM_F64 else (lambda x: x.astype(np.float32))
-    for body in (dgvol.BODY_STAGED, dgvol.BODY_CHUNKREG):
-        Ns = [N for N in sizes if dgvol.body_available(form, oracle.num_nodes(N), body)]
-        trip = [(dev(cast(D[N])), dev(cast(G[N])), dev(cast(u[N]))) for N in Ns]
-        outs = dgvol.dg_volume_batched(trip, form=form, bodies=[body] * len(Ns))
-        for N, o in zip(Ns, outs):
+    for vi in range(6):
+        sizes = {N: 97 + 13 * vi for N in range(1, 8) if vi < dgvol.variant_count(form, oracle.num_nodes(N))}
+        if not sizes:
+            continue
+        D, G, u = _mixed_case(sizes, F, form, 4100 + vi)
+        trip = [(dev(cast(D[N])), dev(cast(G[N])), dev(cast(u[N]))) for N in sizes]
+        outs = dgvol.dg_volume_batched(trip, form=form, variants=[vi] * len(sizes))
+        for N, o in zip(sizes, outs):
             got = host(o)
             if form == dgvol.FORM_F64:
                 check_planes(got, oracle.volume(D[N], G[N], u[N]), forward_cond(D[N], G[N], u[N]))
@@ -571,11 +555,18 @@ def test_autotuner_cache_and_tuned_launch(tmp_path, monkeypatch):
     _say("autotune")
     (tmp_path / "cache.json").write_text("{not json")  # a corrupt cache is ignored and rewritten
     e = autotune.tune(dgvol.FORM_F64, 35, 3, target_bytes=32 << 20, min_tiles=1 << 10, reps=3)
-    assert e["body"] in (0, 1) and e["tile_cost_s"] > 0
-    assert autotune.lookup(dgvol.FORM_F64, 35, 3, tune_missing=False)["body"] == e["body"]
+    n = dgvol.variant_count(dgvol.FORM_F64, 35)
+    assert 0 <= e["variant"] < n and 0 <= e["single_variant"] < n and e["tile_cost_s"] > 0
+    assert set(e["candidates_s_per_tile"]) == {str(v) for v in range(n)}
+    assert autotune.lookup(dgvol.FORM_F64, 35, 3, tune_missing=False)["variant"] == e["variant"]
     sizes = {2: 300, 4: 200, 6: 50}
+    for N in sizes:
+        autotune.tune(dgvol.FORM_F64, oracle.num_nodes(N), 3, target_bytes=16 << 20, min_tiles=1 << 10, reps=3)
     D, G, u = _mixed_case(sizes, 3, dgvol.FORM_F64, 4400)
     trip = [(dev(D[N]), dev(G[N]), dev(u[N])) for N in sizes]
     outs = autotune.volume_batched_tuned(trip)
     for N, o in zip(sizes, outs):
         check_planes(host(o), oracle.volume(D[N], G[N], u[N]), forward_cond(D[N], G[N], u[N]))
+    # the chosen plan is cached under the batch's shapes
+    v, c, times = autotune.plan_batch(trip, dgvol.FORM_F64)
+    assert set(times) == {"default", "tuned", "tuned_variants"} and len(v) == len(c) == 3
