@@ -20,6 +20,10 @@
 //   * per step the workgroup stages u[c][:] and W[c][rows] in LDS, row-major
 //     per column; each thread stages a fixed column, so it needs the
 //     geometric factors of one element only;
+//   * the staging is software-pipelined over two LDS buffers: while the waves
+//     multiply step s out of one buffer, each thread writes step s+1 (loaded
+//     into registers during step s-1) into the other and requests step s+2
+//     from memory, with one barrier per step;
 //   * each workgroup writes its partial gD to work[part]; a second kernel adds
 //     the partials in a fixed order.
 //
@@ -54,18 +58,17 @@ struct GdShape {
   static constexpr int KSPLIT = NTW >= GD_WPB ? 1 : (NTW == 1 ? 8 : (NTW == 2 ? 4 : 2));
   static constexpr int SLOTS = NTW * KSPLIT;            // (tile, k share) pairs
   static constexpr int TPW = (SLOTS + GD_WPB - 1) / GD_WPB;
-  static constexpr int CH = NP <= 10 ? 128 : (NP <= 20 ? 64 : (NP <= 56 ? 32 : 16));
-  // Register prefetch of the next step (measured): it pays at the low orders,
-  // whose steps are short; at Np = 35, 56 the registers it holds are worth
-  // more than the latency it hides.
-  static constexpr bool PREFETCH = !(NP == 35 || NP == 56);
+  // columns per step: two staging buffers of at most 32 KB, so that two
+  // workgroups fit the LDS of a CU
+  static constexpr int CH = NP <= 4 ? 128 : (NP <= 10 ? 64 : (NP <= 35 ? 32 : 16));
   static constexpr int TPC = NTH / CH;                  // threads staging one column
   static constexpr int NXU = (NP + TPC - 1) / TPC;      // values per thread and plane
   static constexpr int LDU = gd_ld(16 * NB);
   static constexpr int LDW = gd_ld(16 * RTS);
-  static constexpr int STAGE_DOUBLES = CH * (LDU + LDW);
+  static constexpr int STAGE_DOUBLES = CH * (LDU + LDW);  // one staging buffer
   static constexpr int RED_DOUBLES = KSPLIT > 1 ? SLOTS * 256 : 0;
-  static constexpr int LDS_DOUBLES = STAGE_DOUBLES > RED_DOUBLES ? STAGE_DOUBLES : RED_DOUBLES;
+  static constexpr int LDS_DOUBLES = 2 * STAGE_DOUBLES > RED_DOUBLES ? 2 * STAGE_DOUBLES : RED_DOUBLES;
+  static_assert(2 * LDS_DOUBLES * 8 <= 160 * 1024, "two workgroups per CU");
   static_assert(GD_UNIT % CH == 0 && CH % 4 == 0, "staging step");
   static_assert((CH / 4) % KSPLIT == 0, "k steps split evenly");
 };
@@ -91,8 +94,7 @@ void gd_partial_kernel(GdArgs p) {
   constexpr int CH = S::CH;
   constexpr int SUB = GD_UNIT / CH;  // steps per partition unit
   __shared__ double lds[S::LDS_DOUBLES];
-  double* ul = lds;                // [CH][LDU]  u[c][j]
-  double* wl = lds + CH * S::LDU;  // [CH][LDW]  W[c][r - r0]
+  // staging buffer b: u[c][j] at [b][c][LDU], W[c][r - r0] at [b][CH LDU + c LDW]
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
@@ -115,7 +117,7 @@ void gd_partial_kernel(GdArgs p) {
 
   // Pad entries (columns Np.. of u, rows r1-r0.. of W) feed only outputs that
   // are never stored; keep them finite.
-  for (int x = tid; x < S::STAGE_DOUBLES; x += S::NTH) lds[x] = 0.0;
+  for (int x = tid; x < 2 * S::STAGE_DOUBLES; x += S::NTH) lds[x] = 0.0;
   __syncthreads();
 
   // this thread's column within a step and its first row
@@ -140,16 +142,10 @@ void gd_partial_kernel(GdArgs p) {
     for (int m = 0; m < 9; ++m) rG[m] = v ? p.G[gb + m] : 0.0;
   };
 
-  f64x4 acc[S::TPW];
-#pragma unroll
-  for (int t = 0; t < S::TPW; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-
-  if constexpr (S::PREFETCH) {
-    if (st_begin < st_end) load(st_begin);
-  }
-  for (uint32_t st = st_begin; st < st_end; ++st) {
-    if constexpr (!S::PREFETCH) load(st);
-    __syncthreads();  // the previous step's products are done with the LDS
+  // write the registers' step into staging buffer b
+  auto stage = [&](int b) __attribute__((always_inline)) {
+    double* ul = lds + b * S::STAGE_DOUBLES;
+    double* wl = ul + CH * S::LDU;
 #pragma unroll
     for (int q = 0; q < S::NXU; ++q) {
       const int i = rr + S::TPC * q;
@@ -163,10 +159,29 @@ void gd_partial_kernel(GdArgs p) {
         }
       }
     }
-    __syncthreads();
-    if constexpr (S::PREFETCH) {
-      if (st + 1 < st_end) load(st + 1);
+  };
+
+  f64x4 acc[S::TPW];
+#pragma unroll
+  for (int t = 0; t < S::TPW; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+
+  // prologue: step st_begin staged in buffer 0, step st_begin + 1 in registers
+  if (st_begin < st_end) {
+    load(st_begin);
+    stage(0);
+    if (st_begin + 1 < st_end) load(st_begin + 1);
+  }
+  __syncthreads();
+  int cur = 0;
+  for (uint32_t st = st_begin; st < st_end; ++st) {
+    // the other buffer was last read by the products of the previous step,
+    // which every wave finished before the barrier that ended it
+    if (st + 1 < st_end) {
+      stage(cur ^ 1);
+      if (st + 2 < st_end) load(st + 2);
     }
+    const double* ul = lds + cur * S::STAGE_DOUBLES;
+    const double* wl = ul + CH * S::LDU;
 #pragma unroll
     for (int t = 0; t < S::TPW; ++t) {
       const int slot = wave * S::TPW + t;
@@ -187,6 +202,8 @@ void gd_partial_kernel(GdArgs p) {
       // into registers for every slot at once
       __builtin_amdgcn_sched_barrier(0);
     }
+    __syncthreads();  // the next step's staging is visible; this buffer is free
+    cur ^= 1;
   }
 
   // Add the k shares of each tile (fixed order) and store the partial sum.

@@ -309,12 +309,13 @@ static uint32_t gd_parts(int64_t K, int32_t Np, int32_t F) {
   return std::min<uint32_t>(nunits, gd_maxpart(Np));
 }
 
+// Partial sums of the D cotangent into work[npart][3][Np][Np], then their
+// fixed-order sum into gD.
 template <int NP>
 static dg_status launch_gd_f64(const double* G, const double* u, const double* gout, double* gD, double* work,
-                               int64_t K, int32_t F, hipStream_t stream) {
+                               uint32_t npart, int64_t K, int32_t F, hipStream_t stream) {
   using S = GdShape<NP>;
   const uint64_t ncols = (uint64_t)K * (uint64_t)F;
-  const uint32_t npart = gd_parts(K, NP, F);
   if (npart > 0) {
     const GdArgs p{G, u, gout, work, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP, ceil_div(ncols, GD_UNIT),
                    npart};
@@ -464,7 +465,8 @@ dg_status dg_volume_grad_d(const double* G, const double* u, const double* gout,
     if (!aligned(G, 8) || !aligned(u, 8) || !aligned(gout, 8) || !aligned(work, 8)) return DG_EINVAL;
     if (work_bytes < need) return DG_EINVAL;
   }
-  DGVOL_DISPATCH(launch_gd_f64, G, u, gout, gD, static_cast<double*>(work), K, F, (hipStream_t)stream)
+  DGVOL_DISPATCH(launch_gd_f64, G, u, gout, gD, static_cast<double*>(work), gd_parts(K, Np, F), K, F,
+                 (hipStream_t)stream)
 }
 
 #undef DGVOL_DISPATCH
