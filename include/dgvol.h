@@ -33,7 +33,8 @@
  *   - Arguments are validated before any HIP call; on error nothing is
  *     launched and no output is touched.
  *   - K == 0 is a no-op that returns DG_OK (pointers may then be NULL),
- *     except for dg_volume_grad_d, whose output gD is then set to zero.
+ *     except for dg_volume_grad_d and dg_volume_grad_d_noalloc, whose output
+ *     gD is then set to zero.
  *   - Pointers must be aligned to their element size (8 bytes for double,
  *     4 bytes for float).
  *   - Supported node counts: Np in {4, 10, 20, 35, 56, 84, 120} (N = 1..7).
@@ -56,6 +57,7 @@ typedef int32_t dg_status;
 #define DG_EUNSUPPORTED (-2)  /* Np not a supported node count, or form not available */
 #define DG_ELAUNCH (-3)       /* the HIP launch reported an error */
 #define DG_EDEVICE (-4)       /* querying the current device failed */
+#define DG_ESCRATCH (-5)      /* the problem needs more scratch than a fixed-scratch entry point holds */
 
 #define DGVOL_ABI_VERSION 2
 
@@ -133,6 +135,31 @@ dg_status dg_volume_grad_d(const double *G, const double *u, const double *gout,
 /* Scratch bytes dg_volume_grad_d needs for (K, Np, F), written to *bytes (may
  * be 0).  Pure host computation.  Errors: DG_EINVAL, DG_EUNSUPPORTED. */
 dg_status dg_volume_grad_d_workspace(int64_t K, int32_t Np, int32_t F, uint64_t *bytes);
+
+/*
+ * dg_volume_grad_d for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation).
+ * Same arguments, layouts and result as dg_volume_grad_d without the
+ * workspace: the partial sums go to one fixed scratch array of
+ * DG_GRAD_D_NOALLOC_SCRATCH_BYTES (64 MiB) that the library holds on every
+ * device it runs on, until the process ends.  The partition of the columns is
+ * that of dg_volume_grad_d, so the two give the same gD bit for bit.
+ * A problem whose partial sums need more than the fixed scratch
+ * (dg_volume_grad_d_workspace(K, Np, F) > DG_GRAD_D_NOALLOC_SCRATCH_BYTES,
+ * which happens only at Np = 84 with K*F > 50 688 and at Np = 120 with
+ * K*F > 24 832) is rejected with DG_ESCRATCH before anything is launched.
+ * The call allocates nothing and calls no allocating routine; its first call
+ * on a device looks up that device's copy of the scratch.
+ * Every call on one device shares that device's scratch, which keeps the last
+ * call's partial sums: calls that overlap in time on one device (on different
+ * streams, or from host threads without ordering) race and give wrong
+ * results; order them on one stream.
+ * Errors: as dg_volume_grad_d (with no workspace checks), plus DG_ESCRATCH and
+ *         DG_EDEVICE.
+ */
+#define DG_GRAD_D_NOALLOC_SCRATCH_BYTES (64ull << 20)
+dg_status dg_volume_grad_d_noalloc(const double *G, const double *u, const double *gout, double *gD,
+                                   int64_t K, int32_t Np, int32_t F, void *stream);
 
 /*
  * Forward volume derivative with FP32 storage and split-BF16 products.

@@ -329,6 +329,38 @@ static dg_status launch_gd_f64(const double* G, const double* u, const double* g
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
 
+// ------------------------------------------------------------------ fixed scratch (dg_volume_grad_d_noalloc)
+
+// The partial sums of the D cotangent for callers that cannot allocate.  Each
+// device the library runs on holds its own copy until the process ends.  In
+// host code `scratch` names a host-side stand-in, not device memory: kernels
+// and copies get the device address that scratch_device_ptr() looks up once
+// per device, never the symbol itself.
+static __device__ __align__(256) double scratch[DG_GRAD_D_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+static std::mutex scratch_mutex;
+static double* scratch_dev[MAX_DEVICES];
+
+// Device address of `scratch` on the current device (looked up on the first
+// call per device; the lookup allocates nothing).
+static double* scratch_device_ptr(int* err) {
+  const int dev = current_device(err);
+  if (dev < 0) return nullptr;
+  if (dev >= MAX_DEVICES) {
+    *err = DG_EDEVICE;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(scratch_mutex);
+  if (!scratch_dev[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+      *err = DG_EDEVICE;
+      return nullptr;
+    }
+    scratch_dev[dev] = static_cast<double*>(ptr);
+  }
+  return scratch_dev[dev];
+}
+
 // ------------------------------------------------------------------ validation
 
 static inline bool aligned(const void* p, uintptr_t a) { return ((uintptr_t)p & (a - 1)) == 0; }
@@ -360,6 +392,9 @@ const char* dg_strerror(dg_status s) {
     case DG_EUNSUPPORTED: return "unsupported node count Np (supported: 4, 10, 20, 35, 56, 84, 120), form or body";
     case DG_ELAUNCH: return "kernel launch failed";
     case DG_EDEVICE: return "could not query the current HIP device";
+    case DG_ESCRATCH:
+      return "the problem needs more scratch than the fixed no-allocation buffer holds "
+             "(DG_GRAD_D_NOALLOC_SCRATCH_BYTES); call dg_volume_grad_d with a workspace";
     default: return "unknown status";
   }
 }
@@ -467,6 +502,25 @@ dg_status dg_volume_grad_d(const double* G, const double* u, const double* gout,
   }
   DGVOL_DISPATCH(launch_gd_f64, G, u, gout, gD, static_cast<double*>(work), gd_parts(K, Np, F), K, F,
                  (hipStream_t)stream)
+}
+
+dg_status dg_volume_grad_d_noalloc(const double* G, const double* u, const double* gout, double* gD, int64_t K,
+                                   int32_t Np, int32_t F, void* stream) {
+  bool noop = false;
+  const dg_status st = check_common(K, Np, F, &noop);
+  if (st != DG_OK) return st;
+  if (!gD || !aligned(gD, 8)) return DG_EINVAL;
+  if (!noop) {
+    if (!G || !u || !gout) return DG_EINVAL;
+    if (!aligned(G, 8) || !aligned(u, 8) || !aligned(gout, 8)) return DG_EINVAL;
+  }
+  uint64_t need = 0;
+  dg_volume_grad_d_workspace(K, Np, F, &need);
+  if (need > DG_GRAD_D_NOALLOC_SCRATCH_BYTES) return DG_ESCRATCH;
+  int err = DG_OK;
+  double* work = scratch_device_ptr(&err);
+  if (err != DG_OK) return err;
+  DGVOL_DISPATCH(launch_gd_f64, G, u, gout, gD, work, gd_parts(K, Np, F), K, F, (hipStream_t)stream)
 }
 
 #undef DGVOL_DISPATCH

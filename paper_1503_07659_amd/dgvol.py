@@ -1,7 +1,7 @@
 """Python binding of libdgvol.so (argument marshalling only).
 
 The functions named like the C entry points (``dg_volume``,
-``dg_volume_adjoint``, ``dg_volume_grad_d``, ``dg_volume_f32s``,
+``dg_volume_adjoint``, ``dg_volume_grad_d``, ``dg_volume_grad_d_noalloc``, ``dg_volume_f32s``,
 ``dg_volume_variant``, ``dg_volume_batched`` and the two calibration calls) take torch tensors on the
 GPU, check dtype/device/shape/contiguity, and pass raw device pointers plus
 torch's current HIP stream to the library.  Every arithmetic step runs in the
@@ -26,6 +26,10 @@ DG_EINVAL = -1
 DG_EUNSUPPORTED = -2
 DG_ELAUNCH = -3
 DG_EDEVICE = -4
+DG_ESCRATCH = -5
+
+# fixed scratch of dg_volume_grad_d_noalloc (DG_GRAD_D_NOALLOC_SCRATCH_BYTES)
+GRAD_D_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 SUPPORTED_NP = (4, 10, 20, 35, 56, 84, 120)
 
@@ -93,6 +97,8 @@ def load_library(path=None):
     lib.dg_volume_adjoint.restype = I32
     lib.dg_volume_grad_d.argtypes = [P, P, P, P, P, ctypes.c_uint64, I64, I32, I32, P]
     lib.dg_volume_grad_d.restype = I32
+    lib.dg_volume_grad_d_noalloc.argtypes = [P, P, P, P, I64, I32, I32, P]
+    lib.dg_volume_grad_d_noalloc.restype = I32
     lib.dg_volume_grad_d_workspace.argtypes = [I64, I32, I32, ctypes.POINTER(ctypes.c_uint64)]
     lib.dg_volume_grad_d_workspace.restype = I32
     lib.dg_volume_f32s.argtypes = [P, P, P, P, I64, I32, I32, P]
@@ -222,6 +228,24 @@ def dg_volume_grad_d(G, u, gout, gD=None, work=None):
         st = load_library().dg_volume_grad_d(G.data_ptr(), u.data_ptr(), gout.data_ptr(), gD.data_ptr(),
                                              work.data_ptr(), nbytes, K, Np, F, _stream_handle(dev))
     _raise_on(st, "dg_volume_grad_d")
+    return gD
+
+
+def dg_volume_grad_d_noalloc(G, u, gout, gD):
+    """dg_volume_grad_d through the library's fixed scratch: the call allocates nothing (the
+    caller passes the output gD).  Raises DGVolError with status DG_ESCRATCH for a problem
+    whose partial sums exceed GRAD_D_NOALLOC_SCRATCH_BYTES.  Calls that overlap in time on
+    one device share its scratch and race."""
+    _check_tensor("u", u, torch.float64, tuple(u.shape))
+    K, F, Np = _sizes(u)
+    dev = u.device
+    _check_tensor("G", G, torch.float64, (K, 9), dev)
+    _check_tensor("gout", gout, torch.float64, (3, K, F, Np), dev)
+    _check_tensor("gD", gD, torch.float64, (3, Np, Np), dev)
+    with torch.cuda.device(dev):
+        st = load_library().dg_volume_grad_d_noalloc(G.data_ptr(), u.data_ptr(), gout.data_ptr(), gD.data_ptr(),
+                                                     K, Np, F, _stream_handle(dev))
+    _raise_on(st, "dg_volume_grad_d_noalloc")
     return gD
 
 

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 def test_version_and_strerror(lib):
     assert lib.dg_abi_version() == 2
-    for st in (0, -1, -2, -3, -4, -99):
+    for st in (0, -1, -2, -3, -4, -5, -99):
         msg = lib.dg_strerror(st)
         assert isinstance(msg, bytes) and msg
     assert [lib.dg_supported_np(n) for n in (4, 10, 20, 35, 56, 84, 120)] == [1] * 7
@@ -116,6 +116,35 @@ def test_grad_d_workspace_and_validation(lib):
         assert f(*ptrs, need, 100, 35, 3, None) == dgvol.DG_EINVAL
     # K == 0 still writes gD (zeros), so it needs gD, but nothing else
     assert f(FAKE, FAKE, FAKE, None, FAKE, 0, 0, 35, 3, None) == dgvol.DG_EINVAL
+
+
+def test_grad_d_noalloc_validation(lib):
+    """The fixed-scratch entry point validates like dg_volume_grad_d and rejects, before any
+    HIP call, a problem whose partial sums exceed its 64 MiB scratch."""
+    f = lib.dg_volume_grad_d_noalloc
+    cap = dgvol.GRAD_D_NOALLOC_SCRATCH_BYTES
+    assert cap == 64 << 20
+    assert f(FAKE, FAKE, FAKE, FAKE, -1, 35, 3, None) == dgvol.DG_EINVAL
+    assert f(FAKE, FAKE, FAKE, FAKE, 100, 35, 0, None) == dgvol.DG_EINVAL
+    assert f(FAKE, FAKE, FAKE, FAKE, 100, 34, 3, None) == dgvol.DG_EUNSUPPORTED
+    assert f(FAKE, FAKE, FAKE, None, 0, 35, 3, None) == dgvol.DG_EINVAL   # gD is written even for K == 0
+    for i in range(4):
+        ptrs = [FAKE] * 4
+        ptrs[i] = None
+        assert f(*ptrs, 100, 35, 3, None) == dgvol.DG_EINVAL
+        ptrs[i] = FAKE + 4
+        assert f(*ptrs, 100, 35, 3, None) == dgvol.DG_EINVAL
+    # the largest problems that fit (header: K*F <= 50 688 at Np = 84, <= 24 832 at Np = 120),
+    # and one column more, which is rejected
+    for Np, cols in ((84, 50688), (120, 24832)):
+        assert dgvol.grad_d_workspace_bytes(cols, Np, 1) <= cap
+        assert dgvol.grad_d_workspace_bytes(cols + 1, Np, 1) > cap
+        assert f(FAKE, FAKE, FAKE, FAKE, cols + 1, Np, 1, None) == dgvol.DG_ESCRATCH
+        assert f(FAKE, FAKE, FAKE, FAKE, (cols + 1) * 4, Np, 4, None) == dgvol.DG_ESCRATCH
+    # every problem size fits at Np <= 56
+    for Np in (4, 10, 20, 35, 56):
+        assert dgvol.grad_d_workspace_bytes(1 << 24, Np, 16) <= cap
+    assert b"scratch" in lib.dg_strerror(dgvol.DG_ESCRATCH)
 
 
 def test_mfma_calibrate_validation(lib):
