@@ -14,10 +14,16 @@ cores on a bounded sample, and the split-BF16 form and the adjoint measured
 beside it.
 
 Profiling helpers (used to produce the committed counter summaries):
-    python bench.py --profile-run                  # 1 GiB copy x3, then the forward kernel x3
+    python bench.py --profile-run
+        # 1 GiB copy x3, the order-4 forward x3, then the FP64 kernels of the order-5, -6 and -7
+        # lines (forward, adjoint, cotangent of D) x3 each
     python bench.py --summarize-counters FETCH_DIR WRITE_DIR
         # reads two `rocprofv3 --pmc FETCH_SIZE` / `--pmc WRITE_SIZE` output trees of
         # --profile-run and writes the HBM traffic summary under profiles/
+    python bench.py --summarize-mfma DIR
+        # reads a `rocprofv3 --kernel-trace --pmc SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE
+        # SQ_INSTS_VALU_MFMA_MOPS_F64 SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE` tree of --profile-run
+        # and writes the matrix-core utilisation summary under profiles/
 """
 
 import argparse
@@ -39,8 +45,12 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFS = 78.6           # MI355X FP64 (vector and matrix)
 KERNEL_SRC_DIR = os.path.join(ROOT, "paper_1503_07659_amd", "csrc")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_dg_volume_fwd_f64_order4_K1048576_F5.txt")
-FWD_KERNEL_TAG = "fwd_f64_kernel<35, 0>"
-COPY_KERNEL_TAG = "stream_kernel"
+FWD_KERNEL_TAG = "fwd_f64_kernel<35, 0, 8, 1>"
+COPY_KERNEL_TAG = "stream16_kernel"
+MFMA_FILE = os.path.join(ROOT, "profiles", "mfma_util_fp64_kernels.md")
+SIMD_NUM = 1024  # MI355X: 256 CUs x 4 SIMDs
+NXCD = 8         # MI355X: 8 XCDs
+CLOCK_GHZ = 2.4  # MI355X peak engine clock
 WORKLOAD = dict(N=4, K=1 << 20, F=5)
 PROFILE_COPY_DOUBLES = 1 << 27  # 1 GiB copy for counter calibration
 
@@ -267,9 +277,10 @@ def workload_inputs():
 
 
 def profile_run():
-    """Known-size copy (counter scale) followed by the forward kernel, three launches each."""
+    """Known-size copy (counter scale), the order-4 forward, then the FP64 kernels of the order-5,
+    -6 and -7 lines; three launches each."""
     import torch
-    from paper_1503_07659_amd import dgvol
+    from paper_1503_07659_amd import dgvol, setup_host, synth
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     src = torch.ones(PROFILE_COPY_DOUBLES, dtype=torch.float64, device=dev)
@@ -284,6 +295,26 @@ def profile_run():
     for _ in range(3):
         dgvol.dg_volume(Dd, Gd, ud, out=out)
     torch.cuda.synchronize()
+    del Dd, Gd, ud, out
+    torch.cuda.empty_cache()
+    for N, K, F in ((5, 1 << 19, 3), (6, 1 << 17, 3), (7, 132228, 3)):
+        Np = setup_host.NODE_COUNTS[N]
+        D5 = torch.from_numpy(setup_host.reference_matrices(N)).to(dev)
+        G5 = torch.from_numpy(setup_host.geometric_factors(synth.tet_vertices(K, synth.mesh_seed(5) + N))).to(dev)
+        u5 = torch.from_numpy(synth.fields(K, F, Np, synth.field_seed(5) + N, "uniform")).to(dev)
+        o5 = torch.empty((3, K, F, Np), dtype=torch.float64, device=dev)
+        for _ in range(3):
+            dgvol.dg_volume(D5, G5, u5, out=o5)
+        g5 = 2.0 * o5
+        gu5, gG5 = torch.empty_like(u5), torch.empty_like(G5)
+        for _ in range(3):
+            dgvol.dg_volume_adjoint(D5, G5, u5, g5, gu=gu5, gG=gG5)
+        if N == 5:
+            for _ in range(3):
+                dgvol.dg_volume_grad_d(G5, u5, g5)
+        torch.cuda.synchronize()
+        del D5, G5, u5, o5, g5, gu5, gG5
+        torch.cuda.empty_cache()
     print("profile run done", flush=True)
 
 
@@ -330,7 +361,7 @@ def summarize_counters(fetch_dir, write_dir):
         fh.write("#   rocprofv3 --pmc FETCH_SIZE -d <fetch_dir> --output-format csv -- python bench.py --profile-run\n")
         fh.write("#   rocprofv3 --pmc WRITE_SIZE -d <write_dir> --output-format csv -- python bench.py --profile-run\n")
         fh.write("#   python bench.py --summarize-counters <fetch_dir> <write_dir>\n")
-        fh.write("# Counter units are scaled by a 1 GiB copy (stream_kernel, copies=1) in the same runs.\n")
+        fh.write("# Counter units are scaled by a 1 GiB copy (stream16_kernel, copies=1) in the same runs.\n")
         fh.write(f"kernel_source_sha256: {kernel_source_sha()}\n")
         fh.write(f"copy_fetch_counter_per_launch: {np.median(cf):.1f}\n")
         fh.write(f"copy_write_counter_per_launch: {np.median(cw):.1f}\n")
@@ -346,6 +377,64 @@ def summarize_counters(fetch_dir, write_dir):
     print(open(TRAFFIC_FILE).read())
 
 
+def summarize_mfma(root):
+    """Matrix-core use per FP64 kernel of --profile-run: MFMA-busy cycles over (GUI-active cycles
+    x SIMDs), executed FP64 matrix flops per second over the spec peak, and LDS bank-conflict
+    cycles over LDS-active cycles; medians over each kernel's dispatches."""
+    rows = _counter_rows(root)
+    trace = {}
+    for path in glob.glob(os.path.join(root, "**", "*kernel_trace*.csv"), recursive=True):
+        with open(path, newline="") as fh:
+            for r in csv.DictReader(fh):
+                trace[r.get("Dispatch_Id") or r.get("Correlation_Id")] = \
+                    (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-9
+    per = {}
+    for r in rows:
+        key = r.get("Dispatch_Id") or r.get("Correlation_Id")
+        ent = per.setdefault(key, {"name": r.get("Kernel_Name", "")})
+        ent[r["Counter_Name"]] = ent.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    # GRBM_GUI_ACTIVE counts per XCD and the csv sums the instances: cycles = sum / NXCD
+    by_kernel = {}
+    for key, ent in per.items():
+        name = ent["name"]
+        if "fwd_f64" not in name and "adj" not in name and "gd_partial" not in name:
+            continue
+        if "SQ_VALU_MFMA_BUSY_CYCLES" not in ent or "GRBM_GUI_ACTIVE" not in ent:
+            continue
+        cycles = ent["GRBM_GUI_ACTIVE"] / NXCD
+        util = ent["SQ_VALU_MFMA_BUSY_CYCLES"] / (cycles * SIMD_NUM)
+        flops = ent.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512
+        per_cycle = FP64_PEAK_TFS * 1e12 / (CLOCK_GHZ * 1e9)
+        frac = flops / (cycles * per_cycle)
+        lds = ent.get("SQ_LDS_BANK_CONFLICT", 0.0) / max(ent.get("SQ_LDS_IDX_ACTIVE", 0.0), 1.0)
+        dur = trace.get(key, float("nan"))
+        by_kernel.setdefault(name.split("(")[0], []).append((util, frac, lds, dur, flops))
+    os.makedirs(os.path.dirname(MFMA_FILE), exist_ok=True)
+    with open(MFMA_FILE, "w") as fh:
+        fh.write("# Matrix-core use of the FP64 kernels (rocprofv3 counters, MI355X)\n\n")
+        fh.write("Commands (GPU box, TMPDIR=/tmp, run from /tmp):\n\n")
+        fh.write("    rocprofv3 --kernel-trace --pmc SQ_VALU_MFMA_BUSY_CYCLES GRBM_GUI_ACTIVE SQ_INSTS_VALU_MFMA_MOPS_F64 "
+                 "SQ_LDS_BANK_CONFLICT SQ_LDS_IDX_ACTIVE -d <dir> -f csv -- python3 <repo>/bench.py --profile-run\n")
+        fh.write("    python3 <repo>/bench.py --summarize-mfma <dir>\n\n")
+        fh.write("* MFMA busy = SQ_VALU_MFMA_BUSY_CYCLES / (active cycles x 1024 SIMDs), rocprofv3's MfmaUtil; "
+                 "active cycles = GRBM_GUI_ACTIVE / 8 (the csv sums the counter over the 8 XCDs).\n")
+        fh.write("* executed of peak = SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 FP64 matrix flops (padding rows included) "
+                 "over (active cycles x the spec peak per cycle, 78.6 TFLOP/s at 2.4 GHz): clock-independent. "
+                 "The profile run launches each kernel three times without warm-up, so its wall durations "
+                 "(last column) run long; the bench line gives the warm times.\n")
+        fh.write("* LDS conflict = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE.\n")
+        fh.write("* Workloads: order 4 K=2^20 F=5; order 5 K=2^19 F=3; order 6 K=2^17 F=3; order 7 K=132228 F=3.\n\n")
+        fh.write("| kernel | dispatches | MFMA busy | executed of FP64 peak | executed GFLOP per launch | "
+                 "LDS conflict | median ms (profiled) |\n")
+        fh.write("|---|---|---|---|---|---|---|\n")
+        for name in sorted(by_kernel):
+            v = np.array(by_kernel[name])
+            med = np.median(v, axis=0)
+            fh.write(f"| `{name}` | {len(v)} | {med[0]:.3f} | {med[1]:.3f} | {med[4] / 1e9:.2f} | "
+                     f"{med[2]:.3f} | {med[3] * 1e3:.4f} |\n")
+    print(open(MFMA_FILE).read())
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -356,9 +445,13 @@ def main():
     ap.add_argument("--cpu-elements", type=int, default=1 << 18)
     ap.add_argument("--profile-run", action="store_true")
     ap.add_argument("--summarize-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"))
+    ap.add_argument("--summarize-mfma", metavar="DIR")
     args = ap.parse_args()
     if args.summarize_counters:
         summarize_counters(*args.summarize_counters)
+        return
+    if args.summarize_mfma:
+        summarize_mfma(args.summarize_mfma)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}): the volume kernel "
@@ -380,6 +473,29 @@ def main():
     Dd, Gd, ud = (torch.from_numpy(x).to(dev) for x in (D, G, u))
     out = torch.empty((3, K, F, Np), dtype=torch.float64, device=dev)
 
+    # Calibrations first (they also bring the GPU to its working clocks before the timed
+    # steps): practical streaming ceiling for the same bytes in the same 1 : 3 read : write mix
+    n_u = ud.numel()
+    _, per_c = time_launches(lambda: dgvol.dg_stream_calibrate(ud.view(-1), out.view(-1), 3), 10, 2, torch,
+                             min_warm_ms=WARM_MS)
+    ceil_gbs = 4 * n_u * 8 / (float(np.median(per_c)) * 1e-3) / 1e9
+    _, per_1 = time_launches(lambda: dgvol.dg_stream_calibrate(ud.view(-1), out.view(-1)[:n_u], 1), 10, 2, torch,
+                             min_warm_ms=WARM_MS)
+    copy_gbs = 2 * n_u * 8 / (float(np.median(per_1)) * 1e-3) / 1e9
+    # the forward's own data movement (tiles through LDS, no arithmetic) in its persistent launch
+    # shape and as a one-pass grid
+    tile_gbs = {}
+    for tag, m in (("persistent", 0), ("one_pass", 1)):
+        _, per_t = time_launches(lambda: dgvol.dg_stream_calibrate_tiles(ud.view(-1), out.view(-1), m), 10, 2,
+                                 torch, min_warm_ms=WARM_MS)
+        tile_gbs[tag] = round(4 * n_u * 8 / (float(np.median(per_t)) * 1e-3) / 1e9, 1)
+    # attainable FP64 matrix-core rate: independent MFMA chains from registers
+    sink, _ = dgvol.dg_mfma_calibrate(10)
+    _, per_m = time_launches(lambda: dgvol.dg_mfma_calibrate(10000, sink=sink), 5, 1, torch, min_warm_ms=WARM_MS)
+    cal_flops = dgvol.MFMA_CAL_BLOCKS * 4 * 10000 * 4 * 2048
+    mfma_tfs = cal_flops / (float(np.median(per_m)) * 1e-3) / 1e12
+    del sink
+
     def step():
         dgvol.dg_volume(Dd, Gd, ud, out=out)
 
@@ -392,21 +508,6 @@ def main():
     bytes_launch = K * fwd_bytes_per_element(F, Np)
     flops_launch = K * fwd_flops_per_element(F, Np)
     achieved = bytes_launch / (kern_ms * 1e-3) / 1e9
-
-    # practical streaming ceiling for the same bytes in the same 1 : 3 read : write mix
-    n_u = ud.numel()
-    _, per_c = time_launches(lambda: dgvol.dg_stream_calibrate(ud.view(-1), out.view(-1), 3), 10, 2, torch,
-                             min_warm_ms=WARM_MS)
-    ceil_gbs = 4 * n_u * 8 / (float(np.median(per_c)) * 1e-3) / 1e9
-    _, per_1 = time_launches(lambda: dgvol.dg_stream_calibrate(ud.view(-1), out.view(-1)[:n_u], 1), 10, 2, torch,
-                             min_warm_ms=WARM_MS)
-    copy_gbs = 2 * n_u * 8 / (float(np.median(per_1)) * 1e-3) / 1e9
-    # attainable FP64 matrix-core rate: independent MFMA chains from registers
-    sink, _ = dgvol.dg_mfma_calibrate(10)
-    _, per_m = time_launches(lambda: dgvol.dg_mfma_calibrate(10000, sink=sink), 5, 1, torch, min_warm_ms=WARM_MS)
-    cal_flops = dgvol.MFMA_CAL_BLOCKS * 4 * 10000 * 4 * 2048
-    mfma_tfs = cal_flops / (float(np.median(per_m)) * 1e-3) / 1e12
-    del sink
 
     rec = {
         "metric": METRIC,
@@ -433,6 +534,8 @@ def main():
                      "measured_stream_ceiling_1r3w_GBs": round(ceil_gbs, 1),
                      "frac_of_measured_ceiling": round(achieved / ceil_gbs, 4),
                      "measured_copy_GBs": round(copy_gbs, 1),
+                     "measured_tile_stream_GBs": tile_gbs,
+                     "frac_of_persistent_tile_stream": round(achieved / tile_gbs["persistent"], 4),
                      "fp64_tflops": round(flops_launch / (kern_ms * 1e-3) / 1e12, 2),
                      "fp64_frac": round(flops_launch / (kern_ms * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
                      "measured_fp64_mfma_TFs": round(mfma_tfs, 2)},

@@ -90,6 +90,12 @@ int32_t dg_supported_np(int32_t Np);
  *   G    [K][9]        geometric factors (read)
  *   u    [K][F][Np]    nodal values (read)
  *   out  [3][K][F][Np] written: out[b][k][f][i] = sum_a G[k][3a+b] (D_a u[k][f])[i]
+ * Source: the volume term of a nodal DG discretisation on affine elements, the
+ * solver use case of the paper's Introduction (which gives no formula: this
+ * is the chain rule through the element's affine map).  D is staged on chip
+ * once per workgroup, the paper's precompute of a repeatedly fetched operand
+ * (Section 4.3); the product is the matrix-matrix multiplication of
+ * Section 5.2 with both operands staged through on-chip memory.
  * Errors: DG_EINVAL (null pointer with K > 0, K < 0, F < 1, misaligned),
  *         DG_EUNSUPPORTED (Np), DG_ELAUNCH.
  */
@@ -102,7 +108,10 @@ dg_status dg_volume(const double *D, const double *G, const double *u, double *o
  *   gu[k][f][j]  = sum_a sum_i D[a][i][j] * W_a[i],  W_a[i] = sum_b G[k][3a+b] gout[b][k][f][i]
  *   gG[k][3a+b]  = sum_f sum_i gout[b][k][f][i] * (D_a u[k][f])[i]
  *   gout [3][K][F][Np] (read), gu [K][F][Np] (written), gG [K][9] (written).
- * D_a u is recomputed, not read.  Errors as for dg_volume.
+ * D_a u is recomputed, not read.
+ * Source: defined by this library, not by the paper: the reverse-mode
+ * derivative of dg_volume, which is linear in u and in G.
+ * Errors as for dg_volume.
  */
 dg_status dg_volume_adjoint(const double *D, const double *G, const double *u,
                             const double *gout, double *gu, double *gG,
@@ -125,6 +134,8 @@ dg_status dg_volume_adjoint(const double *D, const double *G, const double *u,
  * The columns are split into a number of partial sums fixed by (K, F) alone
  * and added in a fixed order, so the result is the same bit for bit on every
  * run and every device.  No D argument: gD does not depend on D.
+ * Source: defined by this library, not by the paper (reverse mode of the
+ * matrix product in dg_volume).
  * Errors: DG_EINVAL (null or misaligned pointer, work_bytes too small,
  *         K < 0, F < 1), DG_EUNSUPPORTED (Np), DG_ELAUNCH.
  */
@@ -169,6 +180,8 @@ dg_status dg_volume_grad_d_noalloc(const double *G, const double *u, const doubl
  * on BF16 matrix cores with FP32 accumulation, and the G combine runs in FP32.
  * Stated accuracy against the FP64 result on the same (FP64) data: per output
  * plane, max|err| <= 2e-5 max|ref| and ||err||_2 <= 1e-5 ||ref||_2.
+ * Source: a precision form defined by this library, not by the paper; the
+ * data movement is that of dg_volume (Sections 4.3 and 5.2).
  * Errors as for dg_volume.
  */
 dg_status dg_volume_f32s(const float *D, const float *G, const float *u, float *out,
@@ -205,6 +218,9 @@ typedef struct dg_group {
  * gets at least one; Jefferson apportionment).  The split is static: the launch
  * needs no device-side state and can be captured in a HIP graph.  Each group's out is exactly what dg_volume /
  * dg_volume_f32s would write for that group alone.
+ * Source: the batching is this library's; the per-order choice of launch
+ * shapes is the paper's autotuning use case (Introduction) applied to tile
+ * shapes.
  * Errors: DG_EINVAL (ngroups outside 0..DG_MAX_GROUPS, F < 1, NULL groups
  * with ngroups > 0, a group failing the dg_volume argument checks),
  * DG_EUNSUPPORTED (form, Np or a variant not available for the form and order),
@@ -292,6 +308,25 @@ dg_status dg_launch_shape_query(int32_t op, int32_t form, int32_t Np, int32_t va
  * DG_ELAUNCH.
  */
 dg_status dg_stream_calibrate(const double *src, double *dst, int64_t n, int32_t copies, void *stream);
+
+/*
+ * Tile-stream calibration (not part of the DG computation): the data movement
+ * of the order-4 FP64 forward (dg_volume at Np = 35) without its arithmetic.
+ * src holds ntiles tiles of 560 doubles (16 columns x 35 nodes), dst three
+ * planes of the same size: dst[c * 560 ntiles + 560 t + x] = (c + 1) src[560 t + x].
+ * Every 64-lane wave moves whole tiles through its own LDS buffer as the
+ * forward kernel does (one contiguous run in, three runs out, two LDS round
+ * trips), prefetching the next tile's run before the current one's stores.
+ * tiles_per_wave = m >= 1: a grid of ceil(ntiles / 8m) 8-wave workgroups, each
+ * wave taking m tiles (m = 1: the grid covers the array once);
+ * tiles_per_wave = 0: one 8-wave workgroup per CU looping over all tiles, the
+ * launch shape of the forward kernel.  Timed by the caller, it separates the
+ * cost of the launch shape from the cost of the arithmetic.
+ * Errors: DG_EINVAL (ntiles < 0 or too large, tiles_per_wave < 0, null or
+ * misaligned pointer with ntiles > 0), DG_EDEVICE, DG_ELAUNCH.
+ */
+dg_status dg_stream_calibrate_tiles(const double *src, double *dst, int64_t ntiles, int32_t tiles_per_wave,
+                                    void *stream);
 
 /*
  * FP64 matrix-core calibration (not part of the DG computation).  Launches

@@ -1,6 +1,7 @@
 // The __global__ entry kernels of the library: single-group forward kernels
-// (FP64, split-BF16), the mixed-order batched kernels and the bandwidth and
-// matrix-core calibration kernels, with the per-form LDS sizes their launches use.  The
+// (FP64, split-BF16) and the mixed-order batched kernels, with the per-form
+// LDS sizes their launches use.  The bandwidth and matrix-core calibration
+// kernels are in dgvol_calibrate.hpp.  The
 // adjoint and D-cotangent kernels live with their bodies (dgvol_adjoint.hpp,
 // dgvol_gradd.hpp); the host-side launch code and the C ABI are in
 // dgvol_kernels.hip.
@@ -174,77 +175,5 @@ __attribute__((amdgpu_waves_per_eu(class_min_waves_per_eu(C), 8))) void batched_
 }
 #undef DGVOL_BCASE64
 #undef DGVOL_BCASE32
-
-// ------------------------------------------------------------------ stream calibration
-//
-// Reads n doubles once and writes `copies` scaled copies of them (dst[c*n + i]
-// = (c + 1) * src[i]), with streaming (non-temporal) stores as the forward
-// kernels store their output planes.  With copies = 1 this is a plain copy of
-// known size (the scale of the hardware byte counters); with copies = 3 it
-// moves bytes in the forward kernel's 1 : 3 read : write mix with no other
-// work (the streaming ceiling for that mix).
-//
-// stream16_kernel: one pass, no loop: every thread moves STREAM_U independent
-// 16-byte pairs (all loads issued before any store), and the grid covers the
-// array once (hundreds of thousands of workgroups for the workload sizes).
-// stream_kernel: the fallback for arrays that are not 16-byte aligned or of
-// odd length, one 8-byte word per lane in a grid-stride loop.
-constexpr int STREAM_U = 4;
-constexpr int STREAM_BLOCK = 256;
-typedef double f64x2 __attribute__((ext_vector_type(2)));
-
-__global__ __launch_bounds__(STREAM_BLOCK) void stream16_kernel(const f64x2* __restrict__ src,
-                                                                f64x2* __restrict__ dst, int64_t n2,
-                                                                int32_t copies) {
-  const int64_t base = (int64_t)blockIdx.x * (STREAM_BLOCK * STREAM_U) + threadIdx.x;
-  f64x2 v[STREAM_U];
-#pragma unroll
-  for (int q = 0; q < STREAM_U; ++q) {
-    const int64_t i = base + (int64_t)STREAM_BLOCK * q;
-    v[q] = i < n2 ? src[i] : f64x2{0.0, 0.0};
-  }
-  for (int32_t c = 0; c < copies; ++c) {
-    const double s = (double)(c + 1);
-#pragma unroll
-    for (int q = 0; q < STREAM_U; ++q) {
-      const int64_t i = base + (int64_t)STREAM_BLOCK * q;
-      if (i < n2) __builtin_nontemporal_store(v[q] * s, &dst[c * n2 + i]);
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void stream_kernel(const double* __restrict__ src, double* __restrict__ dst,
-                                                     int64_t n, int32_t copies) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const double v = src[i];
-    for (int32_t c = 0; c < copies; ++c) store_stream(&dst[c * n + i], (double)(c + 1) * v);
-  }
-}
-
-// ------------------------------------------------------------------ matrix-core calibration
-//
-// Every wave runs `iters` rounds of four independent accumulator chains of
-// v_mfma_f64_16x16x4f64 with register operands (no memory traffic in the
-// loop), then writes one sum per lane, so the work cannot be dropped.  Each
-// product depends on the previous one of its chain; the operands stay fixed
-// (rewriting a source register of an MFMA in flight would stall the issue).
-// Launched with 256 threads; the wider bound keeps the accumulators in VGPRs
-// (with a 256-thread bound the compiler moves them through AGPRs every round).
-__global__ __launch_bounds__(1024) void mfma_cal_kernel(double* __restrict__ sink, int32_t iters) {
-  const int lane = threadIdx.x & 63;
-  const double a = 1.0 + 1e-3 * lane, b = 1.0 - 1e-3 * lane;
-  f64x4 c0 = f64x4{0.0, 0.0, 0.0, 0.0}, c1 = c0, c2 = c0, c3 = c0;
-  for (int32_t it = 0; it < iters; ++it) {
-    c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c0, 0, 0, 0);
-    c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c1, 0, 0, 0);
-    c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, c2, 0, 0, 0);
-    c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, b, c3, 0, 0, 0);
-  }
-  double s = 0.0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) s += c0[q] + c1[q] + c2[q] + c3[q];
-  sink[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
-}
 
 }  // namespace dgvol

@@ -7,7 +7,8 @@
 // the forward data-movement schemes in dgvol_forward.hpp (FP64) and
 // dgvol_forward_f32s.hpp (split-BF16), the adjoint in
 // dgvol_adjoint.hpp, the D cotangent in dgvol_gradd.hpp, the register layout
-// of the products in dgvol_layout.hpp, the entry kernels in dgvol_global.hpp.
+// of the products in dgvol_layout.hpp, the entry kernels in dgvol_global.hpp,
+// the calibration kernels in dgvol_calibrate.hpp.
 // This file holds the host side: launch configuration, validation, the ABI.
 #include <hip/hip_runtime.h>
 
@@ -20,6 +21,7 @@
 #include "dgvol.h"
 #include "dgvol_adjoint.hpp"
 #include "dgvol_adjoint_cr.hpp"
+#include "dgvol_calibrate.hpp"
 #include "dgvol_device.hpp"
 #include "dgvol_forward.hpp"
 #include "dgvol_forward_f32s.hpp"
@@ -703,6 +705,37 @@ dg_status dg_stream_calibrate(const double* src, double* dst, int64_t n, int32_t
   const int64_t want = (n + 255) / 256;
   const uint32_t grid = (uint32_t)std::min<int64_t>(want, (int64_t)cus * 64);
   hipLaunchKernelGGL(stream_kernel, dim3(grid), dim3(256), 0, (hipStream_t)stream, src, dst, n, copies);
+  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+}
+
+dg_status dg_stream_calibrate_tiles(const double* src, double* dst, int64_t ntiles, int32_t tiles_per_wave,
+                                    void* stream) {
+  if (ntiles < 0 || ntiles > INT32_MAX / TSTREAM_TILE || tiles_per_wave < 0) return DG_EINVAL;
+  if (ntiles == 0) return DG_OK;
+  if (!src || !dst || !aligned(src, 8) || !aligned(dst, 8)) return DG_EINVAL;
+  // dynamic LDS: the waves' tile buffers, or (persistent form) enough to hold one
+  // workgroup per CU, as the order-4 forward kernel's registers do
+  const int need = TSTREAM_WPB * TSTREAM_TILE * 8;
+  const int lds = tiles_per_wave == 0 ? 100 * 1024 : need;
+  const uint64_t waves_needed = (uint64_t)ntiles;
+  uint32_t grid, iters;
+  if (tiles_per_wave == 0) {
+    int err = DG_OK;
+    const int dev = current_device(&err);
+    if (dev < 0) return err;
+    const int cus = cu_count(dev, &err);
+    if (err != DG_OK) return err;
+    grid = (uint32_t)std::min<uint64_t>((uint64_t)cus, ceil_div(waves_needed, TSTREAM_WPB));
+  } else {
+    grid = ceil_div(waves_needed, (uint64_t)TSTREAM_WPB * (uint64_t)tiles_per_wave);
+  }
+  iters = ceil_div((uint64_t)ntiles, (uint64_t)grid * TSTREAM_WPB);
+  static std::atomic<bool> attr{false};
+  if (!attr.exchange(true))
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_stream_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  hipLaunchKernelGGL(tile_stream_kernel, dim3(grid), dim3(WAVE * TSTREAM_WPB), (size_t)lds, (hipStream_t)stream, src,
+                     dst, (uint32_t)ntiles, (int64_t)ntiles * TSTREAM_TILE, iters);
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
 

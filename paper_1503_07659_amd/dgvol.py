@@ -105,6 +105,8 @@ def load_library(path=None):
     lib.dg_volume_f32s.restype = I32
     lib.dg_stream_calibrate.argtypes = [P, P, I64, I32, P]
     lib.dg_stream_calibrate.restype = I32
+    lib.dg_stream_calibrate_tiles.argtypes = [P, P, I64, I32, P]
+    lib.dg_stream_calibrate_tiles.restype = I32
     lib.dg_mfma_calibrate.argtypes = [P, I32, P]
     lib.dg_mfma_calibrate.restype = I32
     lib.dg_volume_batched.argtypes = [ctypes.POINTER(DgGroup), I32, I32, I32, P]
@@ -359,6 +361,27 @@ def dg_stream_calibrate(src, dst, copies):
 
 
 MFMA_CAL_BLOCKS = 2048
+
+
+TILE_STREAM_WORDS = 16 * 35  # doubles per tile of dg_stream_calibrate_tiles
+
+
+def dg_stream_calibrate_tiles(src, dst, tiles_per_wave):
+    """Tile-stream calibration: src (ntiles * 560 doubles), dst (3 * ntiles * 560 doubles);
+    tiles_per_wave = 0 is the forward's persistent launch shape, m >= 1 a grid of m tiles per wave."""
+    for name, t in (("src", src), ("dst", dst)):
+        if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or t.device.type != "cuda" \
+                or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous float64 GPU tensor")
+    if src.numel() % TILE_STREAM_WORDS:
+        raise ValueError(f"src must hold whole tiles of {TILE_STREAM_WORDS} doubles")
+    ntiles = src.numel() // TILE_STREAM_WORDS
+    if dst.numel() != 3 * src.numel():
+        raise ValueError("dst must hold three planes of src's size")
+    with torch.cuda.device(src.device):
+        st = load_library().dg_stream_calibrate_tiles(src.data_ptr(), dst.data_ptr(), ntiles, int(tiles_per_wave),
+                                                      _stream_handle(src.device))
+    _raise_on(st, "dg_stream_calibrate_tiles")
 
 
 def dg_mfma_calibrate(iters, sink=None):

@@ -147,6 +147,18 @@ def test_grad_d_noalloc_validation(lib):
     assert b"scratch" in lib.dg_strerror(dgvol.DG_ESCRATCH)
 
 
+def test_stream_calibrate_tiles_validation(lib):
+    f = lib.dg_stream_calibrate_tiles
+    assert f(None, None, 0, 1, None) == dgvol.DG_OK           # nothing to move
+    assert f(FAKE, FAKE, -1, 1, None) == dgvol.DG_EINVAL
+    assert f(FAKE, FAKE, 10, -1, None) == dgvol.DG_EINVAL
+    assert f(FAKE, FAKE, (1 << 31) // 560 + 1, 1, None) == dgvol.DG_EINVAL   # 560 ntiles words >= 2^31
+    assert f(None, FAKE, 10, 1, None) == dgvol.DG_EINVAL
+    assert f(FAKE, None, 10, 0, None) == dgvol.DG_EINVAL
+    assert f(FAKE + 4, FAKE, 10, 1, None) == dgvol.DG_EINVAL
+    assert f(FAKE, FAKE + 4, 10, 1, None) == dgvol.DG_EINVAL
+
+
 def test_mfma_calibrate_validation(lib):
     assert lib.dg_mfma_calibrate(None, 10, None) == dgvol.DG_EINVAL
     assert lib.dg_mfma_calibrate(FAKE + 4, 10, None) == dgvol.DG_EINVAL

@@ -439,6 +439,21 @@ def test_stream_calibrate():
         assert torch.equal(dst, want)
 
 
+@pytest.mark.parametrize("tiles_per_wave", [0, 1, 3])
+def test_stream_calibrate_tiles(tiles_per_wave):
+    """Every tile of every plane written once, scaled by the plane index + 1: the persistent shape
+    (0: one workgroup per CU looping over 10007 tiles), one tile per wave, and three per wave with
+    a ragged last workgroup."""
+    ntiles = 10007
+    _say(f"tile stream calibrate ntiles={ntiles} tiles_per_wave={tiles_per_wave}")
+    w = dgvol.TILE_STREAM_WORDS
+    src = torch.arange(ntiles * w, dtype=torch.float64, device="cuda") * 0.25 - 3.0
+    dst = torch.full((3 * ntiles * w,), float("nan"), dtype=torch.float64, device="cuda")
+    dgvol.dg_stream_calibrate_tiles(src, dst, tiles_per_wave)
+    want = torch.cat([(c + 1) * src for c in range(3)])
+    assert torch.equal(dst, want)
+
+
 # ------------------------------------------------------------------ mixed-order batched launch
 
 def test_mfma_calibrate():
