@@ -216,9 +216,9 @@ def source_sha():
 
 def mixed_orders(torch, dev):
     """Orders 1..7 in one persistent launch (group sizes round(2^U(10,18)), seed 3004), F = 3,
-    FP64 and split-BF16: eager default launch, autotuned launch, graph replay of the tuned
-    launch, and one launch per order for comparison; roofline = sum over groups of
-    max(bytes / HBM peak, flops / matrix peak)."""
+    FP64 and split-BF16: eager default launch (one launch for all groups), one launch per
+    variant class, the autotuned plan, a graph replay of the tuned plan, and one launch per order
+    for comparison; roofline = sum over groups of max(bytes / HBM peak, flops / matrix peak)."""
     from paper_1503_07659_amd import autotune, dgvol, setup_host, synth
     from paper_1503_07659_amd.graph import CapturedLaunch
     F = 3
@@ -237,10 +237,13 @@ def mixed_orders(torch, dev):
         outs = [torch.empty((3,) + tuple(t[2].shape), dtype=dt, device=dev) for t in trip]
         ms_auto, _ = time_launches(lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs), 20, 3, torch,
                                    min_warm_ms=WARM_MS)
+        ms_by_class, _ = time_launches(lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs, by_class=True),
+                                       20, 3, torch, min_warm_ms=WARM_MS)
         # tuning (untimed): every variant of every order, then whole candidate plans on these groups
-        variants, costs, cand = autotune.plan_batch(trip, form, outs=outs)
+        plan = autotune.plan_batch(trip, form, outs=outs)
+        variants, costs, cand = plan.variants, plan.costs, plan.candidates
         tuned = lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs, variants=variants,  # noqa: E731
-                                                costs=costs)
+                                                costs=costs, by_class=plan.by_class)
         ms_tuned, _ = time_launches(tuned, 20, 3, torch, min_warm_ms=WARM_MS)
         cap = CapturedLaunch(tuned)
         ms_graph, _ = time_launches(cap.replay, 20, 3, torch, min_warm_ms=WARM_MS)
@@ -255,6 +258,8 @@ def mixed_orders(torch, dev):
                         K * fwd_flops_per_element(F, Np) / peak)
         res[name] = {"GDOF/s": round(dofs / (ms_graph * 1e-3) / 1e9, 3), "graph_replay_ms": round(ms_graph, 5),
                      "tuned_ms": round(ms_tuned, 5), "default_ms": round(ms_auto, 5),
+                     "default_by_class_ms": round(ms_by_class, 5),
+                     "tuned_mode": "one launch per class" if plan.by_class else "one launch",
                      "one_launch_per_order_ms": round(ms_sep, 5), "roofline_ms": round(roof * 1e3, 5),
                      "frac_of_roofline": round(roof * 1e3 / ms_graph, 4),
                      "variants": {str(N): dict(dgvol.variant_info(form, setup_host.NODE_COUNTS[N],

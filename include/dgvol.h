@@ -59,7 +59,7 @@ typedef int32_t dg_status;
 #define DG_EDEVICE (-4)       /* querying the current device failed */
 #define DG_ESCRATCH (-5)      /* the problem needs more scratch than a fixed-scratch entry point holds */
 
-#define DGVOL_ABI_VERSION 2
+#define DGVOL_ABI_VERSION 3
 
 /* Forms (precisions) of the forward product. */
 #define DG_FORM_F64 0   /* FP64 storage, FP64 matrix cores */
@@ -208,24 +208,30 @@ typedef struct dg_group {
 
 /*
  * Forward volume derivative of up to DG_MAX_GROUPS element groups of
- * possibly different orders, sharing F, in one persistent kernel launch per
- * variant class: each group runs its variant (dg_variant_info.batch_class
- * names the batched kernel that holds it), and a batch whose groups fall into
- * several classes makes one launch per class, in class order, on `stream`.
+ * possibly different orders, sharing F.  `form` is DG_FORM_F64 or
+ * DG_FORM_F32S, optionally ORed with DG_BATCH_BY_CLASS.  Each group runs its
+ * variant.  By default every group whose variant has 8 waves per workgroup
+ * runs in one persistent launch of a kernel that holds all such bodies, side
+ * by side with the others (and 4-wave variants in one more launch).  With
+ * DG_BATCH_BY_CLASS each group runs in the kernel of its variant's class
+ * (dg_variant_info.batch_class), whose register budget fits that class, and
+ * the batch makes one launch per class, in class order, on `stream`.
  * `groups` is a host array of `ngroups` descriptors; it is read during the
- * call only.  The resident workgroups are split between groups by cost x tiles,
- * so that the largest cost per workgroup is as small as possible (every group
- * gets at least one; Jefferson apportionment).  The split is static: the launch
- * needs no device-side state and can be captured in a HIP graph.  Each group's out is exactly what dg_volume /
- * dg_volume_f32s would write for that group alone.
+ * call only.  Within a launch, the resident workgroups are split between
+ * groups by cost x tiles, so that the largest cost per workgroup is as small
+ * as possible (every group gets at least one; Jefferson apportionment).  The
+ * split is static: the launch needs no device-side state and can be captured
+ * in a HIP graph.  Each group's out is exactly what dg_volume_variant would
+ * write for that group alone with the same variant.
  * Source: the batching is this library's; the per-order choice of launch
  * shapes is the paper's autotuning use case (Introduction) applied to tile
  * shapes.
  * Errors: DG_EINVAL (ngroups outside 0..DG_MAX_GROUPS, F < 1, NULL groups
  * with ngroups > 0, a group failing the dg_volume argument checks),
- * DG_EUNSUPPORTED (form, Np or a variant not available for the form and order),
- * DG_EDEVICE, DG_ELAUNCH.  Groups with K = 0 are skipped.
+ * DG_EUNSUPPORTED (form, unknown flag, Np or a variant not available for the
+ * form and order), DG_EDEVICE, DG_ELAUNCH.  Groups with K = 0 are skipped.
  */
+#define DG_BATCH_BY_CLASS 0x100
 dg_status dg_volume_batched(const dg_group *groups, int32_t ngroups, int32_t F, int32_t form, void *stream);
 
 /*
@@ -243,7 +249,7 @@ typedef struct dg_variant_info {
   int32_t body;          /* DG_BODY_STAGED, DG_BODY_CHUNKREG or DG_BODY_STAGED_LEAN */
   int32_t waves;         /* waves (64 lanes) per workgroup */
   int32_t tiles;         /* 16-column tiles per loop iteration (per wave if staged, per workgroup if chunk-register) */
-  int32_t batch_class;   /* the batched kernel that runs it inside dg_volume_batched (0..2) */
+  int32_t batch_class;   /* its class: the batched kernel that runs it under DG_BATCH_BY_CLASS (0..2) */
   int32_t lds_bytes;     /* dynamic LDS per workgroup */
 } dg_variant_info;
 
@@ -288,6 +294,7 @@ typedef struct dg_launch_shape {
 #define DG_OP_FORWARD 0   /* dg_volume_variant(form, variant, ...) */
 #define DG_OP_BATCHED 1   /* dg_volume_batched with one group of this (Np, variant) */
 #define DG_OP_ADJOINT 2   /* dg_volume_adjoint (form must be DG_FORM_F64; variant ignored) */
+#define DG_OP_BATCHED_BY_CLASS 3  /* dg_volume_batched with DG_BATCH_BY_CLASS, one group of this (Np, variant) */
 
 /* Errors: DG_EINVAL (shape NULL, op unknown, K < 1, F < 1), DG_EUNSUPPORTED
  * (form, Np or variant), DG_EDEVICE. */

@@ -10,16 +10,19 @@ Section 3: a search over the transformation parameters of a kernel) applied
 to those tile shapes.
 
 ``tune(form, Np, F)`` times every variant on a synthetic problem large enough
-to fill the GPU, twice: as a single-group launch (``dg_volume_variant``) and
-as a one-group batched launch (the variant runs inside its class's batched
-kernel, whose register budget can differ), and records the fastest of each
-with the measured time of one 16-column tile.  That time is the ``cost`` the
-batched launch uses to split its persistent workgroups between groups.
+to fill the GPU, three ways: as a single-group launch (``dg_volume_variant``)
+and as a one-group batched launch in each of the batched launch modes (the
+default one, whose kernel holds every 8-wave body, and one launch per variant
+class, whose kernel fits the class's register budget).  It records the fastest
+variant of each with the measured time of one 16-column tile.  That time is
+the ``cost`` the batched launch uses to split its persistent workgroups
+between groups.
 
 ``plan_batch(groups, form)`` then measures whole candidate plans on the actual
-groups (the library default, the per-group tuned variants with measured
-costs, and the tuned variants with the library's cost estimate) and keeps the
-fastest, so a tuned batch is never slower than the default one as measured.
+groups -- the library default, the per-group tuned variants with measured
+costs, and the tuned variants with the library's cost estimate, each in both
+launch modes -- and keeps the fastest, so a tuned batch is never slower than
+the default one as measured.
 
 Results are cached in a JSON file (``$DGVOL_AUTOTUNE_CACHE``, default
 ``~/.cache/dgvol/autotune.json``) keyed by the GPU architecture and the
@@ -30,6 +33,7 @@ rewritten.  Tuning needs a GPU; looking up the cache does not.
 import json
 import os
 import tempfile
+from collections import namedtuple
 
 import numpy as np
 import torch
@@ -85,10 +89,10 @@ def _valid_entry(e, form, Np):
     if not isinstance(e, dict):
         return False
     n = dgvol.variant_count(form, Np)
-    for k in ("variant", "single_variant"):
+    for k in ("variant", "single_variant", "by_class_variant"):
         if not isinstance(e.get(k), int) or not 0 <= e[k] < n:
             return False
-    return isinstance(e.get("tile_cost_s"), (int, float)) and e["tile_cost_s"] > 0
+    return all(isinstance(e.get(k), (int, float)) and e[k] > 0 for k in ("tile_cost_s", "by_class_tile_cost_s"))
 
 
 def _synthetic(form, Np, F, K, device):
@@ -127,16 +131,21 @@ def tune(form, Np, F, target_bytes=256 << 20, min_tiles=1 << 15, reps=10, device
     D, G, u = _synthetic(form, Np, F, K, device)
     out = torch.empty((3, K, F, Np), dtype=u.dtype, device=device)
     ntiles = -(-K * F // 16)
-    single, batched = {}, {}
+    single, batched, by_class = {}, {}, {}
     for v in range(dgvol.variant_count(form, Np)):
         single[v] = _median_time(lambda: dgvol.dg_volume_variant(form, v, D, G, u, out=out), reps)
         batched[v] = _median_time(
             lambda: dgvol.dg_volume_batched([(D, G, u)], form=form, outs=[out], variants=[v]), reps)
+        by_class[v] = _median_time(
+            lambda: dgvol.dg_volume_batched([(D, G, u)], form=form, outs=[out], variants=[v], by_class=True), reps)
     best_b = min(batched, key=batched.get)
+    best_c = min(by_class, key=by_class.get)
     best_s = min(single, key=single.get)
     entry = {"variant": int(best_b), "tile_cost_s": batched[best_b] / ntiles,
+             "by_class_variant": int(best_c), "by_class_tile_cost_s": by_class[best_c] / ntiles,
              "single_variant": int(best_s), "single_tile_cost_s": single[best_s] / ntiles,
              "candidates_s_per_tile": {str(v): t / ntiles for v, t in batched.items()},
+             "by_class_candidates_s_per_tile": {str(v): t / ntiles for v, t in by_class.items()},
              "single_candidates_s_per_tile": {str(v): t / ntiles for v, t in single.items()},
              "shapes": {str(v): dgvol.variant_info(form, Np, v) for v in single}, "K": K}
     data = cache if cache is not None else load_cache()
@@ -158,49 +167,63 @@ def lookup(form, Np, F, device=None, cache=None, tune_missing=True):
     return tune(form, Np, F, device=device, cache=data)
 
 
-def plan(groups, form=dgvol.FORM_F64, tune_missing=True):
-    """Per-group variants and measured tile costs for dg_volume_batched from the tuning cache."""
+def plan(groups, form=dgvol.FORM_F64, tune_missing=True, by_class=False):
+    """Per-group variants and measured tile costs for dg_volume_batched (in the given launch mode)
+    from the tuning cache."""
     variants, costs = [], []
     data = load_cache()
+    vk, ck = ("by_class_variant", "by_class_tile_cost_s") if by_class else ("variant", "tile_cost_s")
     for D, G, u in groups:
         K, F, Np = u.shape
         e = lookup(form, Np, F, device=u.device, cache=data, tune_missing=tune_missing)
-        variants.append(dgvol.VARIANT_AUTO if e is None else e["variant"])
-        costs.append(0.0 if e is None else e["tile_cost_s"])
+        variants.append(dgvol.VARIANT_AUTO if e is None else e[vk])
+        costs.append(0.0 if e is None else e[ck])
     return variants, costs
 
 
-def plan_batch(groups, form=dgvol.FORM_F64, outs=None, reps=10, tune_missing=True, save=True):
-    """The fastest measured plan (variants, costs) for this batch of groups.
+BatchPlan = namedtuple("BatchPlan", "variants costs by_class candidates")
 
-    Candidates: the library default (variant 0, estimated costs), the per-group
-    tuned variants with their measured costs, and the tuned variants with the
-    estimated costs.  Each is timed on the actual groups; the result is cached
-    under the batch's shapes.  Returns (variants, costs, {candidate: seconds})."""
+
+def plan_batch(groups, form=dgvol.FORM_F64, outs=None, reps=10, tune_missing=True, save=True):
+    """The fastest measured plan for this batch of groups, as a BatchPlan(variants, costs,
+    by_class, candidates).
+
+    Candidates, each in both launch modes (one launch for all 8-wave groups, and one launch per
+    variant class): the library default (variant 0, estimated costs), the per-group tuned
+    variants with their measured costs, and the tuned variants with the estimated costs.  Each
+    is timed on the actual groups; the result is cached under the batch's shapes.  candidates
+    maps each candidate's name to its measured seconds."""
     device = groups[0][2].device
     data = load_cache()
     key = batch_key(form, groups)
     ns = data.setdefault(device_key(device), {})
     e = ns.get(key)
     n = len(groups)
-    if isinstance(e, dict) and len(e.get("variants", [])) == n and len(e.get("costs", [])) == n:
-        return e["variants"], e["costs"], e.get("candidates_s", {})
+    if isinstance(e, dict) and len(e.get("variants", [])) == n and len(e.get("costs", [])) == n \
+            and isinstance(e.get("by_class"), bool):
+        return BatchPlan(e["variants"], e["costs"], e["by_class"], e.get("candidates_s", {}))
     if outs is None:
         outs = [torch.empty((3,) + tuple(u.shape), dtype=u.dtype, device=device) for _, _, u in groups]
-    tv, tc = plan(groups, form, tune_missing=tune_missing)
-    cands = {"default": ([dgvol.VARIANT_AUTO] * n, [0.0] * n), "tuned": (tv, tc), "tuned_variants": (tv, [0.0] * n)}
-    times = {name: _median_time(lambda: dgvol.dg_volume_batched(groups, form=form, outs=outs, variants=v, costs=c),
-                                reps)
-             for name, (v, c) in cands.items()}
+    cands = {}
+    for bc, suffix in ((False, ""), (True, "_by_class")):
+        tv, tc = plan(groups, form, tune_missing=tune_missing, by_class=bc)
+        cands["default" + suffix] = ([dgvol.VARIANT_AUTO] * n, [0.0] * n, bc)
+        cands["tuned" + suffix] = (tv, tc, bc)
+        cands["tuned_variants" + suffix] = (tv, [0.0] * n, bc)
+    times = {name: _median_time(lambda: dgvol.dg_volume_batched(groups, form=form, outs=outs, variants=v, costs=c,
+                                                                 by_class=bc), reps)
+             for name, (v, c, bc) in cands.items()}
     best = min(times, key=times.get)
-    ns[key] = {"variants": [int(x) for x in cands[best][0]], "costs": [float(x) for x in cands[best][1]],
+    v, c, bc = cands[best]
+    ns[key] = {"variants": [int(x) for x in v], "costs": [float(x) for x in c], "by_class": bool(bc),
                "choice": best, "candidates_s": times}
     if save:
         save_cache(data)
-    return cands[best][0], cands[best][1], times
+    return BatchPlan(v, c, bc, times)
 
 
 def volume_batched_tuned(groups, form=dgvol.FORM_F64, outs=None):
     """dg_volume_batched with the fastest measured plan for these groups."""
-    variants, costs, _ = plan_batch(groups, form, outs=outs)
-    return dgvol.dg_volume_batched(groups, form=form, outs=outs, variants=variants, costs=costs)
+    p = plan_batch(groups, form, outs=outs)
+    return dgvol.dg_volume_batched(groups, form=form, outs=outs, variants=p.variants, costs=p.costs,
+                                   by_class=p.by_class)

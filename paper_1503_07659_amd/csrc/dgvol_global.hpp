@@ -94,8 +94,8 @@ __attribute__((amdgpu_waves_per_eu(min_waves_per_eu(WPB), 8))) void fwd_f32s_ker
 // nothing to reset between launches, so the launch can be captured in a
 // graph).  Block b belongs to the group g with wg_begin[g] <= b < wg_begin[g+1]
 // and runs that group's variant with its rank and count within the group.
-// There is one kernel per variant class (dgvol_variants.hpp); a batch whose
-// groups fall into several classes is one launch per class.
+// There is one kernel per launch class (dgvol_variants.hpp): ALL8 holds every
+// 8-wave variant, the others one variant class each.
 
 constexpr int MAX_GROUPS = DG_MAX_GROUPS;
 
@@ -132,16 +132,19 @@ __device__ __forceinline__ int find_group(const BatchArgs& a) {
 
 constexpr int class_waves(int cls) { return cls == VCLASS_WAVE4 ? 4 : 8; }
 // LIGHT is held to 128 registers per lane (4 waves per SIMD: two 8-wave
-// workgroups per CU), WAVE4 to 168 (three 4-wave workgroups per CU)
+// workgroups per CU), WAVE4 to 168 (three 4-wave workgroups per CU), HEAVY and
+// ALL8 to 256 (the heaviest bodies need them)
 constexpr int class_min_waves_per_eu(int cls) { return cls == VCLASS_LIGHT ? 4 : cls == VCLASS_WAVE4 ? 3 : 2; }
+// whether launch class C runs a variant of class CLS with WPB waves
+constexpr bool class_runs(int C, int CLS, int WPB) { return C == CLS || (C == LCLASS_ALL8 && WPB == 8); }
 
-#define DGVOL_BCASE64(NP, IDX, BODY, WPB, TILES, CLS)                                   \
-  case vkey(NP, IDX):                                                                   \
-    if constexpr (CLS == C) fwd_f64_body<NP, BODY, WPB, TILES>(p, bid, nblk, lds);     \
+#define DGVOL_BCASE64(NP, IDX, BODY, WPB, TILES, CLS)                                                \
+  case vkey(NP, IDX):                                                                                \
+    if constexpr (class_runs(C, CLS, WPB)) fwd_f64_body<NP, BODY, WPB, TILES>(p, bid, nblk, lds);    \
     break;
-#define DGVOL_BCASE32(NP, IDX, BODY, WPB, TILES, CLS)                                   \
-  case vkey(NP, IDX):                                                                   \
-    if constexpr (CLS == C) fwd_f32s_body<NP, BODY, WPB, TILES>(p, bid, nblk, lds);    \
+#define DGVOL_BCASE32(NP, IDX, BODY, WPB, TILES, CLS)                                                \
+  case vkey(NP, IDX):                                                                                \
+    if constexpr (class_runs(C, CLS, WPB)) fwd_f32s_body<NP, BODY, WPB, TILES>(p, bid, nblk, lds);   \
     break;
 
 template <int C>

@@ -168,20 +168,29 @@ static inline uint32_t workers_per_block(const VariantDesc& d) {
   return d.body != BODY_CHUNKREG ? (uint32_t)d.wpb : 1u;
 }
 
-// The batched kernel of a class.
+// The batched kernel of a launch class.
 static const void* batched_fn(int form, int cls) {
   if (form == DG_FORM_F64) {
     switch (cls) {
       case VCLASS_LIGHT: return reinterpret_cast<const void*>(batched_f64_kernel<VCLASS_LIGHT>);
       case VCLASS_HEAVY: return reinterpret_cast<const void*>(batched_f64_kernel<VCLASS_HEAVY>);
-      default: return reinterpret_cast<const void*>(batched_f64_kernel<VCLASS_WAVE4>);
+      case VCLASS_WAVE4: return reinterpret_cast<const void*>(batched_f64_kernel<VCLASS_WAVE4>);
+      default: return reinterpret_cast<const void*>(batched_f64_kernel<LCLASS_ALL8>);
     }
   }
   switch (cls) {
     case VCLASS_LIGHT: return reinterpret_cast<const void*>(batched_f32s_kernel<VCLASS_LIGHT>);
     case VCLASS_HEAVY: return reinterpret_cast<const void*>(batched_f32s_kernel<VCLASS_HEAVY>);
-    default: return reinterpret_cast<const void*>(batched_f32s_kernel<VCLASS_WAVE4>);
+    case VCLASS_WAVE4: return reinterpret_cast<const void*>(batched_f32s_kernel<VCLASS_WAVE4>);
+    default: return reinterpret_cast<const void*>(batched_f32s_kernel<LCLASS_ALL8>);
   }
+}
+
+// The launch class a group of variant d runs in: its variant class when the
+// batch asks for one launch per class, else ALL8 for every 8-wave variant.
+static inline int launch_class(const VariantDesc& d, bool by_class) {
+  if (by_class) return d.cls;
+  return d.wpb == 8 ? LCLASS_ALL8 : VCLASS_WAVE4;
 }
 
 // Persistent grid of a single-group launch of variant d over `ntiles` tiles.
@@ -527,8 +536,12 @@ dg_status dg_volume_grad_d_noalloc(const double* G, const double* u, const doubl
 
 #undef DGVOL_DISPATCH
 
-dg_status dg_volume_batched(const dg_group* groups, int32_t ngroups, int32_t F, int32_t form, void* stream) {
+dg_status dg_volume_batched(const dg_group* groups, int32_t ngroups, int32_t F, int32_t form_flags,
+                            void* stream) {
   if (ngroups < 0 || ngroups > DG_MAX_GROUPS || F < 1) return DG_EINVAL;
+  if (form_flags & ~(0xff | DG_BATCH_BY_CLASS)) return DG_EUNSUPPORTED;
+  const bool by_class = (form_flags & DG_BATCH_BY_CLASS) != 0;
+  const int32_t form = form_flags & 0xff;
   if (form != DG_FORM_F64 && form != DG_FORM_F32S) return DG_EUNSUPPORTED;
   if (ngroups > 0 && !groups) return DG_EINVAL;
   const uintptr_t word = form == DG_FORM_F64 ? 8 : 4;
@@ -548,7 +561,7 @@ dg_status dg_volume_batched(const dg_group* groups, int32_t ngroups, int32_t F, 
     if (!aligned(gr.D, word) || !aligned(gr.G, word) || !aligned(gr.u, word) || !aligned(gr.out, word))
       return DG_EINVAL;
   }
-  for (int cls = 0; cls < NUM_VCLASSES; ++cls) {
+  for (int cls = 0; cls < NUM_LCLASSES; ++cls) {
     BatchArgs a{};
     a.F = (uint32_t)F;
     double cost[DG_MAX_GROUPS];
@@ -557,7 +570,7 @@ dg_status dg_volume_batched(const dg_group* groups, int32_t ngroups, int32_t F, 
     int lds = 0;
     int ng = 0;
     for (int i = 0; i < ngroups; ++i) {
-      if (!live[i] || desc[i].cls != cls) continue;
+      if (!live[i] || launch_class(desc[i], by_class) != cls) continue;
       const dg_group& gr = groups[i];
       const uint64_t ncols = (uint64_t)gr.K * (uint64_t)F;
       GroupDev& gd = a.g[ng];
@@ -626,7 +639,7 @@ dg_status dg_launch_shape_query(int32_t op, int32_t form, int32_t Np, int32_t va
   if ((uint64_t)K * (uint64_t)F > (uint64_t)INT32_MAX) return DG_EINVAL;
   int err = DG_OK;
   dg_launch_shape sh{};
-  if (op == DG_OP_FORWARD || op == DG_OP_BATCHED) {
+  if (op == DG_OP_FORWARD || op == DG_OP_BATCHED || op == DG_OP_BATCHED_BY_CLASS) {
     VariantDesc d;
     if (!variant_desc(form, Np, variant == DG_VARIANT_AUTO ? 0 : variant, &d)) return DG_EUNSUPPORTED;
     const uint32_t ntiles = ceil_div((uint64_t)K * (uint64_t)F, 16);
@@ -636,8 +649,9 @@ dg_status dg_launch_shape_query(int32_t op, int32_t form, int32_t Np, int32_t va
       cap = (uint32_t)resident_blocks_fn(d.fn, WAVE * d.wpb, d.lds, &err);
       sh.block = WAVE * d.wpb;
     } else {
-      sh.block = WAVE * class_waves(d.cls);
-      cap = (uint32_t)resident_blocks_fn(batched_fn(form, d.cls), sh.block, d.lds, &err);
+      const int lc = launch_class(d, op == DG_OP_BATCHED_BY_CLASS);
+      sh.block = WAVE * class_waves(lc);
+      cap = (uint32_t)resident_blocks_fn(batched_fn(form, lc), sh.block, d.lds, &err);
     }
     if (err != DG_OK) return err;
     sh.grid = std::min<uint32_t>(ceil_div(ntiles, per), cap);

@@ -8,9 +8,12 @@
 // is part of the ABI (dg_volume_variant, dg_group.variant).
 //
 // The mixed-order batched launch runs each group's variant inside one of a few
-// batched kernels ("classes"); a class holds the variants with one workgroup
-// size and similar register needs, so that light bodies are not run at the
-// occupancy of the heaviest one.  Class LIGHT is compiled for at most 128
+// batched kernels.  By default every 8-wave variant runs in one kernel that
+// holds them all (the groups then run side by side); on request each group
+// runs in its variant's class kernel ("classes"): a class holds the variants
+// with one workgroup size and similar register needs, so that light bodies
+// are not run at the occupancy of the heaviest one, at the price of one
+// launch per class, one after the other.  Class LIGHT is compiled for at most 128
 // registers per lane (two 8-wave workgroups per CU), HEAVY for at most 256,
 // WAVE4 holds the 4-wave variants, compiled for at most 168 registers per lane
 // (three 4-wave workgroups per CU).
@@ -24,6 +27,11 @@ constexpr int VCLASS_LIGHT = 0;
 constexpr int VCLASS_HEAVY = 1;
 constexpr int VCLASS_WAVE4 = 2;
 constexpr int NUM_VCLASSES = 3;
+// Launch classes of the batched kernels: the three variant classes, plus ALL8,
+// which holds every 8-wave variant (the default batched launch runs all
+// 8-wave groups side by side in one launch of it).
+constexpr int LCLASS_ALL8 = NUM_VCLASSES;
+constexpr int NUM_LCLASSES = NUM_VCLASSES + 1;
 
 constexpr int VB_S = 0;  // DG_BODY_STAGED
 constexpr int VB_C = 1;  // DG_BODY_CHUNKREG

@@ -44,6 +44,10 @@ MAX_GROUPS = 16
 OP_FORWARD = 0
 OP_BATCHED = 1
 OP_ADJOINT = 2
+OP_BATCHED_BY_CLASS = 3
+
+# dg_volume_batched: one launch per variant class instead of one launch for all 8-wave groups
+BATCH_BY_CLASS = 0x100
 
 
 class DgGroup(ctypes.Structure):
@@ -308,9 +312,10 @@ def launch_shape(op, form, Np, variant, K, F):
     return {f: int(getattr(sh, f)) for f, _ in DgLaunchShape._fields_}
 
 
-def dg_volume_batched(groups, form=FORM_F64, outs=None, variants=None, costs=None):
-    """Forward derivative of several element groups (possibly different orders), one persistent
-    launch per variant class.
+def dg_volume_batched(groups, form=FORM_F64, outs=None, variants=None, costs=None, by_class=False):
+    """Forward derivative of several element groups (possibly different orders): one persistent
+    launch for every group with an 8-wave variant (and one for 4-wave variants), or, with
+    by_class, one launch per variant class.
 
     groups: sequence of (D, G, u) tensor triples sharing F and the form's dtype
     (float64 for FORM_F64, float32 for FORM_F32S).  outs: optional matching
@@ -343,7 +348,8 @@ def dg_volume_batched(groups, form=FORM_F64, outs=None, variants=None, costs=Non
         arr[gi].D, arr[gi].G, arr[gi].u, arr[gi].out = D.data_ptr(), G.data_ptr(), u.data_ptr(), out.data_ptr()
         arr[gi].cost = 0.0 if costs is None else float(costs[gi])
     with torch.cuda.device(dev):
-        st = load_library().dg_volume_batched(arr, len(groups), int(F), int(form), _stream_handle(dev))
+        flags = int(form) | (BATCH_BY_CLASS if by_class else 0)
+        st = load_library().dg_volume_batched(arr, len(groups), int(F), flags, _stream_handle(dev))
     _raise_on(st, "dg_volume_batched")
     return res
 

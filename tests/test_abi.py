@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_version_and_strerror(lib):
-    assert lib.dg_abi_version() == 2
+    assert lib.dg_abi_version() == 3
     for st in (0, -1, -2, -3, -4, -5, -99):
         msg = lib.dg_strerror(st)
         assert isinstance(msg, bytes) and msg
@@ -217,6 +217,9 @@ def test_batched_validation(lib):
     assert f(_groups(2), -1, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL
     assert f(_groups(2), 2, 0, dgvol.FORM_F64, None) == dgvol.DG_EINVAL         # F < 1
     assert f(_groups(2), 2, 3, 7, None) == dgvol.DG_EUNSUPPORTED               # unknown form
+    assert f(_groups(2), 2, 3, dgvol.FORM_F64 | 0x200, None) == dgvol.DG_EUNSUPPORTED   # unknown flag
+    assert f(_groups(2), 2, 3, 7 | dgvol.BATCH_BY_CLASS, None) == dgvol.DG_EUNSUPPORTED
+    assert f(_groups(3, K=0), 3, 3, dgvol.FORM_F32S | dgvol.BATCH_BY_CLASS, None) == dgvol.DG_OK
     assert f(_groups(2, Np=36), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EUNSUPPORTED
     assert f(_groups(2, K=-1), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL
     assert f(_groups(2, ptr=None), 2, 3, dgvol.FORM_F64, None) == dgvol.DG_EINVAL
@@ -306,10 +309,13 @@ def test_autotune_cache_io(tmp_path, monkeypatch):
     assert autotune.load_cache() == {}
     autotune.save_cache({"gfx950/abi2": {"f64/Np35/F3": {"variant": 0, "tile_cost_s": 1e-7}}})
     assert autotune.load_cache()["gfx950/abi2"]["f64/Np35/F3"]["variant"] == 0
-    ok = {"variant": 1, "single_variant": 0, "tile_cost_s": 2e-7}
+    ok = {"variant": 1, "single_variant": 0, "tile_cost_s": 2e-7, "by_class_variant": 2, "by_class_tile_cost_s": 3e-7}
     assert autotune._valid_entry(ok, dgvol.FORM_F64, 35)
+    assert not autotune._valid_entry(dict(ok, by_class_tile_cost_s=0.0), dgvol.FORM_F64, 35)
+    old_entry = {k: v for k, v in ok.items() if not k.startswith("by_class")}
+    assert not autotune._valid_entry(old_entry, dgvol.FORM_F64, 35)   # an entry without both modes is retuned
     assert not autotune._valid_entry(dict(ok, tile_cost_s=-1), dgvol.FORM_F64, 35)
     assert not autotune._valid_entry(dict(ok, variant="x"), dgvol.FORM_F64, 35)
-    assert not autotune._valid_entry(dict(ok, variant=1), dgvol.FORM_F64, 120)  # order 7 has one FP64 variant
+    assert not autotune._valid_entry(dict(ok, variant=1, by_class_variant=0), dgvol.FORM_F64, 120)  # one FP64 variant
     assert not autotune._valid_entry(dict(ok, single_variant=99), dgvol.FORM_F64, 35)
     assert autotune.entry_key(1, 120, 3) == "f32s/Np120/F3"

@@ -506,8 +506,9 @@ def test_batched_matches_single_and_oracle(form):
 
 @pytest.mark.parametrize("form", [dgvol.FORM_F64, dgvol.FORM_F32S])
 def test_batched_every_variant_one_launch(form):
-    """Every variant of every order in one batch (one launch per variant class, the groups of
-    a class sharing its workgroups) gives the oracle's result."""
+    """Every variant of every order in one batch, in both launch modes (one launch for all
+    8-wave groups; one launch per variant class), gives the oracle's result, the same bits in
+    both modes."""
     F = 2
     _say(f"batched variants form={form}")
     cast = (lambda x: x) if form == dgvol.FORM_F64 else (lambda x: x.astype(np.float32))
@@ -518,7 +519,9 @@ def test_batched_every_variant_one_launch(form):
         D, G, u = _mixed_case(sizes, F, form, 4100 + vi)
         trip = [(dev(cast(D[N])), dev(cast(G[N])), dev(cast(u[N]))) for N in sizes]
         outs = dgvol.dg_volume_batched(trip, form=form, variants=[vi] * len(sizes))
-        for N, o in zip(sizes, outs):
+        by_class = dgvol.dg_volume_batched(trip, form=form, variants=[vi] * len(sizes), by_class=True)
+        for (N, o), oc in zip(zip(sizes, outs), by_class):
+            assert np.array_equal(host(o), host(oc)), f"order {N} variant {vi}: launch modes differ"
             got = host(o)
             if form == dgvol.FORM_F64:
                 check_planes(got, oracle.volume(D[N], G[N], u[N]), forward_cond(D[N], G[N], u[N]))
@@ -583,5 +586,8 @@ def test_autotuner_cache_and_tuned_launch(tmp_path, monkeypatch):
     for N, o in zip(sizes, outs):
         check_planes(host(o), oracle.volume(D[N], G[N], u[N]), forward_cond(D[N], G[N], u[N]))
     # the chosen plan is cached under the batch's shapes
-    v, c, times = autotune.plan_batch(trip, dgvol.FORM_F64)
-    assert set(times) == {"default", "tuned", "tuned_variants"} and len(v) == len(c) == 3
+    p = autotune.plan_batch(trip, dgvol.FORM_F64)
+    names = {"default", "tuned", "tuned_variants"}
+    assert set(p.candidates) == names | {n + "_by_class" for n in names}
+    assert len(p.variants) == len(p.costs) == 3 and isinstance(p.by_class, bool)
+    assert min(p.candidates.values()) == p.candidates[min(p.candidates, key=p.candidates.get)]

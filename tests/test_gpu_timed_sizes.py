@@ -82,26 +82,26 @@ def _variant_cases():
 
 @pytest.mark.parametrize("form,N,variant", _variant_cases())
 def test_variant_three_loop_iterations(form, N, variant):
-    """One variant, single-group and one-group batched, at >= 3 loop iterations per worker;
-    both against the oracle, and bitwise equal to each other (same body, same arithmetic)."""
+    """One variant, single-group and one-group batched in both launch modes, at >= 3 loop
+    iterations per worker; against the oracle, and bitwise equal to each other (same body, same
+    arithmetic)."""
     Np = oracle.num_nodes(N)
     F = 3
-    K1, sh1 = _k_for_iters(dgvol.OP_FORWARD, form, Np, variant, F)
-    K2, sh2 = _k_for_iters(dgvol.OP_BATCHED, form, Np, variant, F)
-    K = max(K1, K2)
-    sh1 = dgvol.launch_shape(dgvol.OP_FORWARD, form, Np, variant, K, F)
-    sh2 = dgvol.launch_shape(dgvol.OP_BATCHED, form, Np, variant, K, F)
-    _say(f"variant form={form} N={N} v={variant} K={K} F={F} single={sh1} batched={sh2}")
-    assert sh1["min_iters"] >= 3 and sh2["min_iters"] >= 3
-    assert sh1["grid"] <= sh1["resident"] and sh2["grid"] <= sh2["resident"]
+    ops = (dgvol.OP_FORWARD, dgvol.OP_BATCHED, dgvol.OP_BATCHED_BY_CLASS)
+    K = max(_k_for_iters(op, form, Np, variant, F)[0] for op in ops)
+    shapes = [dgvol.launch_shape(op, form, Np, variant, K, F) for op in ops]
+    _say(f"variant form={form} N={N} v={variant} K={K} F={F} single/batched/by-class={shapes}")
+    for sh in shapes:
+        assert sh["min_iters"] >= 3 and sh["grid"] <= sh["resident"]
     D = oracle.derivative_matrices(N)
     G = oracle.geometric_factors(synth.tet_vertices(K, 5000 + 10 * N + variant))
     u = synth.fields(K, F, Np, 5100 + 10 * N + variant, "normal")
     c = _cast(form)
     Dd, Gd, ud = dev(c(D)), dev(c(G)), dev(c(u))
     single = host(dgvol.dg_volume_variant(form, variant, Dd, Gd, ud))
-    batched = host(dgvol.dg_volume_batched([(Dd, Gd, ud)], form=form, variants=[variant])[0])
-    assert np.array_equal(single, batched), "batched launch differs from the single-group launch"
+    for by_class in (False, True):
+        batched = host(dgvol.dg_volume_batched([(Dd, Gd, ud)], form=form, variants=[variant], by_class=by_class)[0])
+        assert np.array_equal(single, batched), f"batched launch (by_class={by_class}) differs from the single one"
     _check_form(form, D, G, u, single.astype(np.float64))
 
 
@@ -168,18 +168,23 @@ def test_mixed_orders_as_benchmarked(form, tmp_path, monkeypatch):
     for (N, (D, G, u)), got in zip(inp.items(), default):
         _say(f"  default plan order {N}")
         _check_form(form, D, G, u, got.astype(np.float64))
+    by_class = [host(o) for o in dgvol.dg_volume_batched(trip, form=form, by_class=True)]
+    for N, got, ref in zip(inp, by_class, default):
+        _say(f"  one launch per class, order {N}")
+        assert np.array_equal(got, ref), f"order {N}: launch modes differ (same variants)"
     for N, _ in inp.items():  # small tuning problems keep the test short
         autotune.tune(form, oracle.num_nodes(N), F, target_bytes=32 << 20, min_tiles=1 << 12, reps=3)
-    variants, costs, times = autotune.plan_batch(trip, form, reps=3)
-    _say(f"  tuned plan variants={variants} candidates={times}")
+    plan = autotune.plan_batch(trip, form, reps=3)
+    variants, costs = plan.variants, plan.costs
+    _say(f"  tuned plan variants={variants} by_class={plan.by_class} candidates={plan.candidates}")
     outs = [torch.full((3,) + tuple(t[2].shape), float("nan"), dtype=t[2].dtype, device="cuda") for t in trip]
-    dgvol.dg_volume_batched(trip, form=form, outs=outs, variants=variants, costs=costs)
+    dgvol.dg_volume_batched(trip, form=form, outs=outs, variants=variants, costs=costs, by_class=plan.by_class)
     tuned = [host(o).copy() for o in outs]
     for (N, (D, G, u)), got in zip(inp.items(), tuned):
         _say(f"  tuned plan order {N}")
         _check_form(form, D, G, u, got.astype(np.float64))
     cap = CapturedLaunch(lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs, variants=variants,
-                                                         costs=costs))
+                                                         costs=costs, by_class=plan.by_class))
     for rep in range(2):
         for o in outs:
             o.fill_(float("nan"))
