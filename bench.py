@@ -613,6 +613,23 @@ def main():
             "adjoint_hbm_frac": round(K5 * adj_bytes_per_element(F5, Np5) / (ka * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
         del D5, G5, u5, o5, g5, gu5, gG5, gD5, wk5
         torch.cuda.empty_cache()
+        # adjoint with more than 16 fields (each element's fields in 16-column sub-tiles)
+        N20, K20, F20 = 5, 1 << 16, 20
+        D20 = torch.from_numpy(setup_host.reference_matrices(N20)).to(dev)
+        G20 = torch.from_numpy(setup_host.geometric_factors(synth.tet_vertices(K20, synth.mesh_seed(5) + 20))).to(dev)
+        u20 = torch.from_numpy(synth.fields(K20, F20, Np5, synth.field_seed(5) + 20, "uniform")).to(dev)
+        g20 = torch.from_numpy(synth.fields(K20, 3 * F20, Np5, synth.field_seed(5) + 21, "normal")).to(dev)
+        g20 = g20.view(K20, 3, F20, Np5).permute(1, 0, 2, 3).contiguous()
+        gu20, gG20 = torch.empty_like(u20), torch.empty_like(G20)
+        _, per20 = time_launches(lambda: dgvol.dg_volume_adjoint(D20, G20, u20, g20, gu=gu20, gG=gG20), 20, 3, torch,
+                                 min_warm_ms=WARM_MS)
+        k20 = float(np.mean(per20))
+        fl20 = K20 * adj_flops_per_element(F20, Np5)
+        forms[f"fp64_adjoint_order5_K{K20}_F{F20}"] = {
+            "adjoint_GDOF/s": round(K20 * F20 * Np5 / (k20 * 1e-3) / 1e9, 3), "adjoint_kernel_ms": round(k20, 5),
+            "adjoint_fp64_frac": round(fl20 / (k20 * 1e-3) / 1e12 / FP64_PEAK_TFS, 4)}
+        del D20, G20, u20, g20, gu20, gG20
+        torch.cuda.empty_cache()
         # adjoint at the orders whose D does not fit LDS (two chunk-register passes)
         for Nh, Kh in ((6, 1 << 17), (7, 1 << 16)):
             Nph = setup_host.NODE_COUNTS[Nh]

@@ -9,155 +9,17 @@
 
 namespace dgvol {
 
-// ------------------------------------------------------------------ adjoint FP64
+// ------------------------------------------------------------------ adjoint FP64 (Np <= 56)
 //
-// Tiles are whole elements: E = max(1, 16 / F) elements per tile, split into
-// nsub sub-tiles of 16 columns (nsub > 1 only when F > 16), so the per-element
-// gG sums need no cross-wave reduction.  Per sub-tile and chunk of 4 node
-// triples: recompute R = D u (forward fragments), read gout at the lane's
-// nodes, accumulate gG partials, form W = G^T gout lane-locally, then feed the
-// 12 W slots straight in as the B operand of the transposed product D^T W
-// (the slot order of W is the k order of that product), accumulated over chunks.
-
-template <int NP, int WPB>
-__global__ __launch_bounds__(WAVE* WPB) void adj_f64_kernel(
-    const double* __restrict__ D, const double* __restrict__ G, const double* __restrict__ u,
-    const double* __restrict__ gout, double* __restrict__ gu, double* __restrict__ gG,
-    uint32_t K, uint32_t F, int64_t plane, uint32_t E, uint32_t nsub, uint32_t ntiles) {
-  using Sh = Shape<NP>;
-  constexpr bool DLDS = 3 * NP * NP * 8 <= 96 * 1024;
-  constexpr int ND = DLDS ? 3 * NP * NP : 1;
-  __shared__ double Dl[ND];
-  __shared__ double red[WPB][16][9];
-  if constexpr (DLDS) {
-    for (int e = threadIdx.x; e < ND; e += WAVE * WPB) Dl[e] = D[e];
-    __syncthreads();
-  }
-  const double* __restrict__ Dsrc = DLDS ? Dl : D;
-  const int lane = threadIdx.x & 63;
-  const int n = lane & 15, g = lane >> 4;
-  const uint32_t wave = threadIdx.x >> 6;
-  for (uint32_t t = blockIdx.x * WPB + wave; t < ntiles; t += gridDim.x * WPB) {
-    const uint32_t k0 = t * E;
-    double P[9];
-#pragma unroll
-    for (int c = 0; c < 9; ++c) P[c] = 0.0;
-    for (uint32_t sub = 0; sub < nsub; ++sub) {
-      const uint32_t lc = sub * 16 + n;
-      const uint32_t e = (F <= 16) ? lc / F : 0u;
-      const uint32_t f = (F <= 16) ? lc - e * F : lc;
-      const uint32_t k = k0 + e;
-      const bool valid = ((F <= 16) ? (lc < E * F) : (lc < F)) && (k < K);
-      const uint32_t col = valid ? k * F + f : 0u;
-      const double* __restrict__ uc = u + (int64_t)col * NP;
-      double b[Sh::KS64];
-#pragma unroll
-      for (int s = 0; s < Sh::KS64; ++s) {
-        const int j = 4 * s + g;
-        b[s] = (valid && j < NP) ? uc[j] : 0.0;
-      }
-      double gk[9];
-#pragma unroll
-      for (int c = 0; c < 9; ++c) gk[c] = valid ? G[(int64_t)k * 9 + c] : 0.0;
-      f64x4 accj[Sh::MTJ];
-#pragma unroll
-      for (int tj = 0; tj < Sh::MTJ; ++tj) accj[tj] = f64x4{0.0, 0.0, 0.0, 0.0};
-      // chunks in a loop, not unrolled: unrolled, the chunks' operands and W
-      // slots overflow the registers (kilobytes of spill at Np = 84)
-#pragma unroll 1
-      for (int ch = 0; ch < Sh::NCHUNK; ++ch) {
-        f64x4 acc[3];
-#pragma unroll
-        for (int tt = 0; tt < 3; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int s = 0; s < Sh::KS64; ++s) {
-#pragma unroll
-          for (int tt = 0; tt < 3; ++tt) {
-            const int T = 3 * ch + tt;
-            if (T < Sh::MT) {
-              const double a = afrag_f64<NP>(Dsrc, T, s, lane);
-              acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b[s], acc[tt], 0, 0, 0);
-            }
-          }
-        }
-        double W[12];
-#pragma unroll
-        for (int x = 0; x < 12; ++x) W[x] = 0.0;
-#pragma unroll
-        for (int xx = 0; xx < 4; ++xx) {
-          const int tau = 4 * ch + xx;
-          if (tau < Sh::TRIP) {
-            double R[3];
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-              const int loc = 3 * xx + a;
-              R[a] = acc[loc >> 2][loc & 3];
-            }
-            const int i = 4 * tau + g;
-            const bool inb = valid && i < NP;
-            double go[3];
-#pragma unroll
-            for (int bb = 0; bb < 3; ++bb)
-              go[bb] = inb ? gout[bb * plane + (int64_t)col * NP + i] : 0.0;
-#pragma unroll
-            for (int a = 0; a < 3; ++a) {
-#pragma unroll
-              for (int bb = 0; bb < 3; ++bb) P[3 * a + bb] += go[bb] * R[a];
-              W[3 * xx + a] = gk[3 * a] * go[0] + gk[3 * a + 1] * go[1] + gk[3 * a + 2] * go[2];
-            }
-          }
-        }
-#pragma unroll
-        for (int sl = 0; sl < 12; ++sl) {
-          const int sp = 12 * ch + sl;
-          if (sp < Sh::SLOTS) {
-#pragma unroll
-            for (int tj = 0; tj < Sh::MTJ; ++tj) {
-              const double a = afragT_f64<NP>(Dsrc, tj, sp, lane);
-              accj[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, W[sl], accj[tj], 0, 0, 0);
-            }
-          }
-        }
-      }
-      double* __restrict__ guc = gu + (int64_t)col * NP;
-#pragma unroll
-      for (int tj = 0; tj < Sh::MTJ; ++tj) {
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int j = 16 * tj + 4 * q + g;
-          if (valid && j < NP) guc[j] = accj[tj][q];
-        }
-      }
-    }
-    // gG: sum the four lane groups (same column), then the columns of each element.
-#pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      P[c] += __shfl_xor(P[c], 16);
-      P[c] += __shfl_xor(P[c], 32);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (g == 0) {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) red[wave][n][c] = P[c];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    if (g == 0 && (uint32_t)n < E && k0 + n < K) {
-      const uint32_t lo = (F <= 16) ? n * F : 0u;
-      const uint32_t hi = (F <= 16) ? lo + F : 16u;
-      for (int c = 0; c < 9; ++c) {
-        double s = 0.0;
-        for (uint32_t m = lo; m < hi; ++m) s += red[wave][m][c];
-        gG[(int64_t)(k0 + n) * 9 + c] = s;
-      }
-    }
-  }
-}
-
-// Staged adjoint kernel (Np <= 56, F <= 16).
+// Tiles are whole elements: E = 16 / F elements per 16-column tile when
+// F <= 16; when F > 16 a tile is one element, taken as ceil(F / 16) sub-tiles
+// of 16 columns in turn by the same wave.  Either way every element's gG sums
+// finish in one wave, in a fixed order, with no cross-wave reduction.  Per
+// (sub-)tile and chunk of 4 node triples: recompute R = D u (forward
+// fragments), read gout at the lane's nodes, accumulate gG partials, form
+// W = G^T gout lane-locally, then feed the 12 W slots straight in as the B
+// operand of the transposed product D^T W (the slot order of W is the k order
+// of that product), accumulated over chunks.
 //
 // The A table of the forward product is stored in LDS with an XOR swizzle
 // (entry `lane` of row (T, s) sits at lane ^ ((s & 3) << 2)).  The forward
@@ -182,11 +44,14 @@ constexpr int adj_staged_lds() {
   return adj_table_rows<NP>() * WAVE * 8 + WPB * 16 * (NP + 1) * 8 + 2 * WPB * 16 * 9 * 8;
 }
 
-template <int NP, int WPB>
+// SUB = false: F <= 16, whole-element tiles of E = 16 / F elements; SUB = true:
+// F > 16, one element per tile in nsub sub-tiles (two instances, so that the
+// common case carries no sub-tile state).
+template <int NP, int WPB, bool SUB>
 __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8))) void adj_f64_staged_kernel(
     const double* __restrict__ D, const double* __restrict__ G, const double* __restrict__ u,
     const double* __restrict__ gout, double* __restrict__ gu, double* __restrict__ gG, uint32_t K, uint32_t F,
-    int64_t plane, uint32_t E, uint32_t ntiles) {
+    int64_t plane, uint32_t E, uint32_t nsub, uint32_t ntiles) {
   using Sh = Shape<NP>;
   constexpr int KS = Sh::KS64;
   constexpr int NFRAG = fwd_table_doubles<NP>();
@@ -229,12 +94,16 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   // compiler then allocates without spilling (measured -15 %).  At the lower
   // orders the guarded form measured 1-4 % faster.
   constexpr bool BUF = NP >= 56;
-  auto load_raw = [&](uint32_t tt) __attribute__((always_inline)) {
+  // the u run of sub-tile ss of tile tt (F <= 16: the whole tile, ss = 0; F > 16: one
+  // element, columns 16 ss .. 16 ss + 15 of it) and the geometric factors of the tile
+  auto load_raw = [&](uint32_t tt, uint32_t ss) __attribute__((always_inline)) {
     const uint32_t kk0 = tt * E;
     if constexpr (BUF) {
       const bool any = tt < ntiles;
       const uint32_t ne = any ? min(E, K - kk0) : 0u;
-      const __amdgpu_buffer_rsrc_t ru = buffer_range(any ? u + (int64_t)kk0 * F * NP : u, ne * F * NP * 8u);
+      const uint32_t ucols = !SUB ? ne * F : (any ? min(16u, F - 16u * ss) : 0u);
+      const uint32_t ubase = kk0 * F + (!SUB ? 0u : 16u * ss);
+      const __amdgpu_buffer_rsrc_t ru = buffer_range(any ? u + (int64_t)ubase * NP : u, ucols * NP * 8u);
 #pragma unroll
       for (int q = 0; q < NRAW; ++q) raw[q] = buffer_load_f64(ru, (uint32_t)(lane + WAVE * q) * 8u);
       const __amdgpu_buffer_rsrc_t rg = buffer_range(any ? G + (int64_t)kk0 * 9 : G, ne * 9 * 8u);
@@ -243,8 +112,9 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
     } else {
       if (tt >= ntiles) return;
       const uint32_t ne = min(E, K - kk0);
-      const double* __restrict__ src = u + (int64_t)kk0 * F * NP;
-      const int cnt = (int)(ne * F) * NP;
+      const uint32_t ucols = !SUB ? ne * F : min(16u, F - 16u * ss);
+      const double* __restrict__ src = u + (int64_t)(kk0 * F + (!SUB ? 0u : 16u * ss)) * NP;
+      const int cnt = (int)ucols * NP;
 #pragma unroll
       for (int q = 0; q < NRAW; ++q) {
         const int x = lane + WAVE * q;
@@ -259,13 +129,16 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
       }
     }
   };
-  load_raw(t);
-  for (; t < ntiles; t += stride) {
+  // gG partial sums of the tile's columns, carried over its sub-tiles
+  double P[9];
+  uint32_t sub = 0;
+  load_raw(t, 0);
+  while (t < ntiles) {
     const uint32_t k0 = t * E;
     const uint32_t ne = min(E, K - k0);
-    const uint32_t ncolt = ne * F;
+    const uint32_t ncolt = !SUB ? ne * F : min(16u, F - 16u * sub);
     const int cnt = (int)ncolt * NP;
-    const uint32_t col0 = k0 * F;
+    const uint32_t col0 = k0 * F + (!SUB ? 0u : 16u * sub);
 #pragma unroll
     for (int q = 0; q < NRAW; ++q) {
       const int x = lane + WAVE * q;
@@ -278,16 +151,17 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
     }
     wave_sync();
     const bool valid = (uint32_t)n < ncolt;
-    const uint32_t e = valid ? (uint32_t)n / F : 0u;
+    const uint32_t e = (valid && !SUB) ? (uint32_t)n / F : 0u;
     const uint32_t col = col0 + (valid ? n : 0);
     const double* ge = gks + e * 9;  // geometric factors of this column's element
     const double* __restrict__ goc = gout + (int64_t)col * NP;
     f64x4 accj[Sh::MTJ];
 #pragma unroll
     for (int tj = 0; tj < Sh::MTJ; ++tj) accj[tj] = f64x4{0.0, 0.0, 0.0, 0.0};
-    double P[9];
+    if (!SUB || sub == 0) {
 #pragma unroll
-    for (int c = 0; c < 9; ++c) P[c] = 0.0;
+      for (int c = 0; c < 9; ++c) P[c] = 0.0;
+    }
 #pragma unroll
     for (int ch = 0; ch < Sh::NCHUNK; ++ch) {
       // this lane's gout values for the chunk, requested before the forward
@@ -404,27 +278,44 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
         if (x < cnt) gdst[x] = stg[(x / NP) * LD + (x % NP)];
       }
     }
-    // gG: four lane groups, then the F columns of each element, in a fixed order
-#pragma unroll
-    for (int c = 0; c < 9; ++c) {
-      P[c] += __shfl_xor(P[c], 16);
-      P[c] += __shfl_xor(P[c], 32);
-    }
-    if (g == 0) {
-#pragma unroll
-      for (int c = 0; c < 9; ++c) red[n * 9 + c] = P[c];
-    }
-    wave_sync();
-    if (g == 0 && (uint32_t)n < ne) {
+    // gG, after the tile's last sub-tile: four lane groups, then the F columns of each
+    // element, in a fixed order
+    const bool last = !SUB || sub + 1 >= nsub;
+    if (last) {
 #pragma unroll
       for (int c = 0; c < 9; ++c) {
-        double sacc = 0.0;
-        for (uint32_t f = 0; f < F; ++f) sacc += red[(n * F + f) * 9 + c];
-        gG[(int64_t)(k0 + n) * 9 + c] = sacc;
+        P[c] += __shfl_xor(P[c], 16);
+        P[c] += __shfl_xor(P[c], 32);
       }
+      if (g == 0) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) red[n * 9 + c] = P[c];
+      }
+      wave_sync();
+      if constexpr (!SUB) {
+        if (g == 0 && (uint32_t)n < ne) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) {
+            double sacc = 0.0;
+            for (uint32_t f = 0; f < F; ++f) sacc += red[(n * F + f) * 9 + c];
+            gG[(int64_t)(k0 + n) * 9 + c] = sacc;
+          }
+        }
+      } else if (lane < 9) {
+        // one element: its 16 lanes carry the partial sums of all its sub-tiles
+        double sacc = 0.0;
+        for (int m = 0; m < 16; ++m) sacc += red[m * 9 + lane];
+        gG[(int64_t)k0 * 9 + lane] = sacc;
+      }
+      wave_sync();
     }
-    wave_sync();
-    load_raw(t + stride);
+    if (last) {
+      t += stride;
+      sub = 0;
+    } else {
+      ++sub;
+    }
+    load_raw(t, SUB ? sub : 0u);
   }
 }
 

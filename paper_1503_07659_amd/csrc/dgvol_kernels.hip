@@ -274,8 +274,8 @@ static dg_status adj_plan(int64_t K, int32_t F, AdjPlan* pl) {
   } else {
     pl->nk = 1;
     pl->block = WAVE * ADJ_WPB;
-    pl->fn[0] = F <= 16 ? reinterpret_cast<const void*>(adj_f64_staged_kernel<NP, ADJ_WPB>)
-                        : reinterpret_cast<const void*>(adj_f64_kernel<NP, ADJ_WPB>);
+    pl->fn[0] = F <= 16 ? reinterpret_cast<const void*>(adj_f64_staged_kernel<NP, ADJ_WPB, false>)
+                        : reinterpret_cast<const void*>(adj_f64_staged_kernel<NP, ADJ_WPB, true>);
     const int cap = resident_blocks_fn(pl->fn[0], pl->block, -1, &err);
     if (err != DG_OK) return err;
     pl->resident[0] = (uint32_t)cap;
@@ -304,11 +304,11 @@ static dg_status launch_adj_f64(const double* D, const double* G, const double* 
                        (uint32_t)F, (int64_t)ncols * NP, E, nsub, ntiles);
   } else {
     if (F <= 16)
-      hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D, G, u,
-                         gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, E, ntiles);
+      hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB, false>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D,
+                         G, u, gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
     else
-      hipLaunchKernelGGL((adj_f64_kernel<NP, ADJ_WPB>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D, G, u, gout,
-                         gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
+      hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB, true>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D,
+                         G, u, gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
   }
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }

@@ -12,7 +12,7 @@ import torch
 
 import oracle
 from paper_1503_07659_amd import dgvol, synth
-from parity import FP64_TOL, adjoint_cond, check_planes, check_whole, forward_cond
+from parity import FP64_TOL, adjoint_cond, adjoint_cond_c, check_planes, check_whole, forward_cond, forward_cond_c
 
 pytestmark = pytest.mark.gpu
 
@@ -150,11 +150,12 @@ def test_adjoint_small(K, F):
         _check_adjoint(D, G, u, gout, host(gu), host(gG))
 
 
-@pytest.mark.parametrize("N", [3, 5, 6, 7])
-def test_adjoint_guard_bands(N):
+@pytest.mark.parametrize("N,F", [(3, 3), (5, 3), (6, 3), (7, 3), (3, 20), (5, 33)])
+def test_adjoint_guard_bands(N, F):
     """gu and gG are written only inside their views (order 5 stores gu through
-    buffer ranges that drop out-of-range lanes; orders 6-7 run two passes)."""
-    K, F = 301, 3
+    buffer ranges that drop out-of-range lanes; orders 6-7 run two passes; F > 16
+    runs each element's fields as 16-column sub-tiles, the last one partial)."""
+    K = 301
     Np = oracle.num_nodes(N)
     _say(f"adjoint guards N={N} K={K} F={F}")
     D, G, u = make_case(N, K, F, 88, "normal")
@@ -186,8 +187,8 @@ def test_adjoint_deterministic(N, K, F):
     _check_adjoint(D, G, u, gout, gu1, gG1)
 
 
-def test_adjoint_workload5_full_size_sampled():
-    """Order 5, K=2^19, F=3, loss = sum(out^2) so gout = 2 out; 2048 sampled elements."""
+def test_adjoint_workload5_full_size():
+    """Order 5, K=2^19, F=3, loss = sum(out^2) so gout = 2 out: every gu and gG entry."""
     N, K, F = 5, 1 << 19, 3
     _say(f"adjoint workload5 N={N} K={K} F={F}")
     D = oracle.derivative_matrices(N)
@@ -197,12 +198,12 @@ def test_adjoint_workload5_full_size_sampled():
     out = dgvol.dg_volume(Dd, Gd, ud)
     gout = 2.0 * out
     gu, gG = dgvol.dg_volume_adjoint(Dd, Gd, ud, gout)
-    idx = np.unique(np.concatenate([np.random.default_rng(5).choice(K, 2048, replace=False), [0, K - 1]]))
-    it = torch.from_numpy(idx).cuda()
-    gout_s = host(gout[:, it])
-    ref_out = oracle.volume(D, G[idx], u[idx])
-    check_planes(gout_s / 2.0, ref_out, forward_cond(D, G[idx], u[idx]))
-    _check_adjoint(D, G[idx], u[idx], gout_s, host(gu[it]), host(gG[it]))
+    gout_h = host(gout)
+    check_planes(gout_h / 2.0, oracle.volume(D, G, u), forward_cond_c(D, G, u))
+    ref_gu, ref_gG = oracle.volume_adjoint(D, G, u, gout_h)
+    c_gu, c_gG = adjoint_cond_c(D, G, u, gout_h)
+    check_whole(host(gu), ref_gu, c_gu, what="gu")
+    check_whole(host(gG), ref_gG, c_gG, what="gG")
 
 
 # ------------------------------------------------------------------ cotangent of D
