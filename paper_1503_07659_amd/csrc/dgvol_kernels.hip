@@ -734,20 +734,20 @@ dg_status dg_stream_calibrate_tiles(const double* src, double* dst, int64_t ntil
   const uint64_t waves_needed = (uint64_t)ntiles;
   uint32_t grid, iters;
   if (tiles_per_wave == 0) {
-    int err = DG_OK;
-    const int dev = current_device(&err);
-    if (dev < 0) return err;
-    const int cus = cu_count(dev, &err);
-    if (err != DG_OK) return err;
+    int cerr = DG_OK;
+    const int dev = current_device(&cerr);
+    if (dev < 0) return cerr;
+    const int cus = cu_count(dev, &cerr);
+    if (cerr != DG_OK) return cerr;
     grid = (uint32_t)std::min<uint64_t>((uint64_t)cus, ceil_div(waves_needed, TSTREAM_WPB));
   } else {
     grid = ceil_div(waves_needed, (uint64_t)TSTREAM_WPB * (uint64_t)tiles_per_wave);
   }
   iters = ceil_div((uint64_t)ntiles, (uint64_t)grid * TSTREAM_WPB);
-  static std::atomic<bool> attr{false};
-  if (!attr.exchange(true))
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(tile_stream_kernel),
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  // raises the kernel's dynamic-LDS limit on this device (once per device)
+  int err = DG_OK;
+  (void)resident_blocks_fn(reinterpret_cast<const void*>(tile_stream_kernel), WAVE * TSTREAM_WPB, lds, &err);
+  if (err != DG_OK) return err;
   hipLaunchKernelGGL(tile_stream_kernel, dim3(grid), dim3(WAVE * TSTREAM_WPB), (size_t)lds, (hipStream_t)stream, src,
                      dst, (uint32_t)ntiles, (int64_t)ntiles * TSTREAM_TILE, iters);
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
