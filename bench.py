@@ -411,7 +411,7 @@ def summarize_mfma(root):
     by_kernel = {}
     for key, ent in per.items():
         name = ent["name"]
-        if "fwd_f64" not in name and "adj" not in name and "gd_partial" not in name:
+        if "fwd_f64" not in name and "adj" not in name and "gd_partial" not in name and "gd_split" not in name:
             continue
         if "SQ_VALU_MFMA_BUSY_CYCLES" not in ent or "GRBM_GUI_ACTIVE" not in ent:
             continue

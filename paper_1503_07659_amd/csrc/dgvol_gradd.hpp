@@ -246,6 +246,190 @@ void gd_partial_kernel(GdArgs p) {
   }
 }
 
+// ------------------------------------------------------------------ order 5: producer and consumer waves
+//
+// At Np = 56 the 44 output tiles (11 stacked row tiles x 4 column blocks) split
+// evenly over the four SIMDs by column block.  The workgroup's waves take two
+// roles: consumer wave jb (0..3, one per SIMD) owns column block jb with all
+// 11 row tiles in its accumulators and reads 12 operands per 11 products;
+// producer waves (4..7) load u, gout and G two steps ahead, form W and stage
+// both into the LDS buffer of the next step.  One barrier per step.  Each
+// output tile accumulates its k steps in column order, so the partial sums
+// depend on (K, F) only.
+struct GdSplit56 {
+  static constexpr int NP = 56;
+  static constexpr int WPB = 8;
+  static constexpr int NTH = WAVE * WPB;
+  static constexpr int NCONS = 4;                    // consumer waves (column blocks)
+  static constexpr int NPRODT = NTH - NCONS * WAVE;  // producer threads
+  static constexpr int NB = 4, RT = 11;
+  static constexpr int CH = 16;                      // columns per step
+  static constexpr int KST = CH / 4;                 // k steps per step
+  static constexpr int LDU = gd_ld(16 * NB);
+  static constexpr int LDW = gd_ld(16 * RT);
+  static constexpr int STAGE_DOUBLES = CH * (LDU + LDW);
+  static constexpr int TPC = NPRODT / CH;            // producer threads per column
+  static constexpr int NXU = (NP + TPC - 1) / TPC;   // values per producer thread and plane
+  static constexpr int DEPTH = 2;                    // steps the loads run ahead
+  static_assert(GD_UNIT % CH == 0, "staging step");
+  static_assert(2 * 2 * STAGE_DOUBLES * 8 <= 160 * 1024, "two workgroups per CU");
+};
+
+__global__ __launch_bounds__(GdSplit56::NTH) __attribute__((amdgpu_waves_per_eu(4, 8)))
+void gd_split56_kernel(GdArgs p) {
+  using S = GdSplit56;
+  constexpr int NP = S::NP;
+  constexpr int CH = S::CH;
+  constexpr int SUB = GD_UNIT / CH;
+  __shared__ double lds[2 * S::STAGE_DOUBLES];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
+  const uint32_t part = blockIdx.x;
+  if (part >= p.npart) return;
+  const uint32_t st_begin = (uint32_t)((uint64_t)part * p.nunits / p.npart) * SUB;
+  const uint32_t st_end = (uint32_t)((uint64_t)(part + 1) * p.nunits / p.npart) * SUB;
+  const uint32_t nsteps = st_end - st_begin;
+
+  // pad entries (columns Np.. of u, rows 3 Np.. of W) stay zero
+  for (int x = tid; x < 2 * S::STAGE_DOUBLES; x += S::NTH) lds[x] = 0.0;
+  __syncthreads();
+
+  const bool consumer = wave < S::NCONS;
+  // ---- producer state: u and gout DEPTH steps ahead (register set r % DEPTH),
+  // the geometric factors one step ahead (one set).  Loads go through buffer
+  // ranges of the column's valid words (past them: zeros, no access), so no
+  // branch surrounds a load and the waits count exactly.
+  const int pt = tid - S::NCONS * WAVE;  // producer thread (valid when !consumer)
+  const int cc = consumer ? 0 : pt / S::TPC;
+  const int rr = consumer ? 0 : pt % S::TPC;
+  double ru[S::DEPTH][S::NXU], rg0[S::DEPTH][S::NXU], rg1[S::DEPTH][S::NXU], rg2[S::DEPTH][S::NXU];
+  double rG[9];
+  // The buffer ranges are the step's (wave-uniform base and size: one
+  // descriptor per wave); a lane's node past Np reads a word of the next
+  // column, which is never staged.
+  auto load_ug = [&](uint32_t r, int d) __attribute__((always_inline)) {
+    const uint32_t c0 = (st_begin + r) * CH;
+    const uint32_t ncl = r < nsteps && c0 < p.ncols ? min((uint32_t)CH, p.ncols - c0) : 0u;
+    const int64_t base = (int64_t)(ncl ? c0 : 0u) * NP;
+    const uint32_t nb = ncl * NP * 8u;
+    const __amdgpu_buffer_rsrc_t bu = buffer_range(p.u + base, nb);
+    const __amdgpu_buffer_rsrc_t b0 = buffer_range(p.gout + base, nb);
+    const __amdgpu_buffer_rsrc_t b1 = buffer_range(p.gout + p.plane + base, nb);
+    const __amdgpu_buffer_rsrc_t b2 = buffer_range(p.gout + 2 * p.plane + base, nb);
+#pragma unroll
+    for (int q = 0; q < S::NXU; ++q) {
+      const uint32_t off = (uint32_t)(cc * NP + rr + S::TPC * q) * 8u;
+      ru[d][q] = buffer_load_f64(bu, off);
+      rg0[d][q] = buffer_load_f64(b0, off);
+      rg1[d][q] = buffer_load_f64(b1, off);
+      rg2[d][q] = buffer_load_f64(b2, off);
+    }
+  };
+  auto load_g = [&](uint32_t r) __attribute__((always_inline)) {
+    const uint32_t c0 = (st_begin + r) * CH;
+    const uint32_t ncl = r < nsteps && c0 < p.ncols ? min((uint32_t)CH, p.ncols - c0) : 0u;
+    const uint32_t k0 = ncl ? c0 / p.F : 0u;
+    const uint32_t nk = ncl ? (c0 + ncl - 1) / p.F - k0 + 1 : 0u;
+    const __amdgpu_buffer_rsrc_t bg = buffer_range(p.G + (int64_t)k0 * 9, nk * 72u);
+    const uint32_t ke = (c0 + (uint32_t)cc) / p.F - k0;  // this lane's element within the step
+#pragma unroll
+    for (int m = 0; m < 9; ++m) rG[m] = buffer_load_f64(bg, (ke * 9u + (uint32_t)m) * 8u);
+  };
+  auto stage = [&](int d, int b) __attribute__((always_inline)) {
+    double* ul = lds + b * S::STAGE_DOUBLES;
+    double* wl = ul + CH * S::LDU;
+#pragma unroll
+    for (int q = 0; q < S::NXU; ++q) {
+      const int i = rr + S::TPC * q;
+      if (i < NP) {
+        ul[cc * S::LDU + i] = ru[d][q];
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          wl[cc * S::LDW + a * NP + i] = rG[3 * a] * rg0[d][q] + rG[3 * a + 1] * rg1[d][q] + rG[3 * a + 2] * rg2[d][q];
+      }
+    }
+  };
+  // Each role runs its own loop (so that the consumers' accumulators and the
+  // producers' register sets are never live together), with the same barriers:
+  // one after the prologue, one per step.  Step r sits in producer register set
+  // r % DEPTH and staging buffer r % 2 (DEPTH = 2: both alternate with r).
+  if (consumer) {
+    // column block jb = wave, all row tiles
+    f64x4 acc[S::RT];
+#pragma unroll
+    for (int t = 0; t < S::RT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+    const double* ub0 = lds + wave * 16 + (lane & 15);
+    const double* wa0 = lds + CH * S::LDU + (lane & 15);
+    __syncthreads();
+    for (uint32_t r = 0; r < nsteps; ++r) {
+      const int b = (int)(r & 1u);
+      const double* ub = ub0 + b * S::STAGE_DOUBLES;
+      const double* wa = wa0 + b * S::STAGE_DOUBLES;
+      // rolling operands: after each product the register of its A operand is
+      // refilled with the next k step's (one LDS read after each product)
+      const int cl = lane >> 4;
+      double av[S::RT];
+      double bv = ub[cl * S::LDU];
+#pragma unroll
+      for (int t = 0; t < S::RT; ++t) av[t] = wa[cl * S::LDW + t * 16];
+#pragma unroll
+      for (int kk = 0; kk < S::KST; ++kk) {
+        const int cn = 4 * (kk + 1) + cl;
+        const double bn = kk + 1 < S::KST ? ub[cn * S::LDU] : 0.0;
+#pragma unroll
+        for (int t = 0; t < S::RT; ++t) {
+          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv, acc[t], 0, 0, 0);
+          if (kk + 1 < S::KST) av[t] = wa[cn * S::LDW + t * 16];
+        }
+#pragma unroll
+        for (int t = 0; t < S::RT; ++t) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one product,
+          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // then one LDS read
+        }
+        __builtin_amdgcn_sched_barrier(0);
+        bv = bn;
+      }
+      __syncthreads();  // the producers have staged step r + 1; buffer r % 2 is free
+    }
+    double* w = p.work + (int64_t)part * 3 * NP * NP;
+    const int j = (int)wave * 16 + (lane & 15);
+#pragma unroll
+    for (int t = 0; t < S::RT; ++t) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = t * 16 + 4 * q + (lane >> 4);
+        if (r < 3 * NP && j < NP) w[(int64_t)r * NP + j] = acc[t][q];
+      }
+    }
+  } else {
+    static_assert(S::DEPTH == 2, "register sets alternate with the step");
+    if (nsteps > 0) {
+      load_ug(0, 0);
+      load_ug(1, 1);
+      load_g(0);
+      stage(0, 0);
+      load_g(1);
+      load_ug(2, 0);
+    }
+    __syncthreads();
+    // iteration r stages step r + 1 (its G requested one iteration earlier, its u and
+    // gout two), then requests G of step r + 2 and u, gout of step r + 3
+    for (uint32_t r0 = 0; r0 < nsteps; r0 += 2) {
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const uint32_t r = r0 + j;
+        if (r < nsteps) {
+          stage(j ^ 1, j ^ 1);
+          load_g(r + 2);
+          load_ug(r + 3, j ^ 1);
+          __syncthreads();
+        }
+      }
+    }
+  }
+}
+
 // gD[x] = sum over parts of work[part][x], x < n, in a fixed order.
 // Block: 64 consecutive x by GD_RED_PG part groups; part group g adds parts
 // g, g + GD_RED_PG, ... in ascending order, and the group sums are then added

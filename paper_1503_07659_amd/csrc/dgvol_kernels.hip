@@ -330,9 +330,13 @@ static dg_status launch_gd_f64(const double* G, const double* u, const double* g
   if (npart > 0) {
     const GdArgs p{G, u, gout, work, (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP, ceil_div(ncols, GD_UNIT),
                    npart};
-    // with NSPLIT > 1 the grid is rounded up to whole groups of 8 ranges (one per XCD)
-    const uint32_t grid = S::NSPLIT == 1 ? npart : ceil_div(npart, 8) * 8 * S::NSPLIT;
-    hipLaunchKernelGGL(gd_partial_kernel<NP>, dim3(grid), dim3(S::NTH), 0, stream, p);
+    if constexpr (NP == 56) {
+      hipLaunchKernelGGL(gd_split56_kernel, dim3(npart), dim3(GdSplit56::NTH), 0, stream, p);
+    } else {
+      // with NSPLIT > 1 the grid is rounded up to whole groups of 8 ranges (one per XCD)
+      const uint32_t grid = S::NSPLIT == 1 ? npart : ceil_div(npart, 8) * 8 * S::NSPLIT;
+      hipLaunchKernelGGL(gd_partial_kernel<NP>, dim3(grid), dim3(S::NTH), 0, stream, p);
+    }
   }
   const uint32_t n = 3u * NP * NP;
   hipLaunchKernelGGL(gd_reduce_kernel, dim3(ceil_div(n, 64)), dim3(64 * GD_RED_PG), 0, stream, work, gD, npart,

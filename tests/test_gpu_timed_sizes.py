@@ -6,8 +6,9 @@
   iterations of its persistent loop, so the prefetch of the next tile and its
   staging are exercised; the size is derived from the launch shape the
   library reports for the device (dg_launch_shape_query).
-* The adjoint at every order, F = 3 (staged / two-pass kernels) and F = 20
-  (general kernel below order 6), at three or more loop iterations.
+* The adjoint at every order, F = 3 and F = 20 (below order 6: 16-column
+  sub-tiles of each element; orders 6, 7: two-pass kernels), at three or more
+  loop iterations.
 * The mixed-order workload exactly as benchmarked (orders 1..7, group sizes
   from seed 3004, F = 3), both forms, with the default plan, the tuned plan
   and a graph replay of the tuned plan.
