@@ -11,6 +11,18 @@
 namespace dgvol {
 
 typedef double f64x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+// The value of lane M of each row of 16 lanes, in every lane of that row
+// (DPP row_newbcast on each 32-bit half).  Every lane of the wave must be active.
+template <int M>
+__device__ __forceinline__ double row_bcast_f64(double v) {
+  static_assert(M >= 0 && M < 16, "lane within a row");
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const int lo = __builtin_amdgcn_mov_dpp((int)(unsigned int)b, 0x150 + M, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_mov_dpp((int)(unsigned int)(b >> 32), 0x150 + M, 0xf, 0xf, false);
+  return __builtin_bit_cast(double, ((unsigned long long)(unsigned int)hi << 32) | (unsigned int)lo);
+}
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 

@@ -31,6 +31,8 @@
 // sum runs in a fixed order, so the result is reproducible bit for bit.
 #pragma once
 
+#include <type_traits>
+
 #include "dgvol_device.hpp"
 
 namespace dgvol {
@@ -248,14 +250,14 @@ void gd_partial_kernel(GdArgs p) {
 
 // ------------------------------------------------------------------ order 5: producer and consumer waves
 //
-// At Np = 56 the 44 output tiles (11 stacked row tiles x 4 column blocks) split
-// evenly over the four SIMDs by column block.  The workgroup's waves take two
-// roles: consumer wave jb (0..3, one per SIMD) owns column block jb with all
-// 11 row tiles in its accumulators and reads 12 operands per 11 products;
-// producer waves (4..7) load u, gout and G two steps ahead, form W and stage
-// both into the LDS buffer of the next step.  One barrier per step.  Each
-// output tile accumulates its k steps in column order, so the partial sums
-// depend on (K, F) only.
+// At Np = 56 the workgroup's waves take two roles.  Consumer waves 0..3 (one
+// per SIMD) hold the output tiles in their accumulators and run the products
+// of each step from LDS (the tiling is described below).  Producer waves
+// 4..7 load u and gout two steps ahead (16-byte accesses of node pairs) and
+// G one step ahead (one factor per lane, handed to the column's 16-lane row
+// by a DPP broadcast), form W and stage both into the LDS buffer of the next
+// step.  One barrier per step.  Each output accumulates its k steps in column
+// order, so the partial sums depend on (K, F) only.
 struct GdSplit56 {
   static constexpr int NP = 56;
   static constexpr int WPB = 8;
@@ -268,12 +270,219 @@ struct GdSplit56 {
   static constexpr int LDU = gd_ld(16 * NB);
   static constexpr int LDW = gd_ld(16 * RT);
   static constexpr int STAGE_DOUBLES = CH * (LDU + LDW);
-  static constexpr int TPC = NPRODT / CH;            // producer threads per column
-  static constexpr int NXU = (NP + TPC - 1) / TPC;   // values per producer thread and plane
+  static constexpr int TPC = NPRODT / CH;            // producer threads per column (one DPP row)
+  static constexpr int NPR = (NP / 2 + TPC - 1) / TPC;  // node pairs per producer thread and plane
+  static constexpr int NXU = 2 * NPR;                // values per producer thread and plane
   static constexpr int DEPTH = 2;                    // steps the loads run ahead
   static_assert(GD_UNIT % CH == 0, "staging step");
   static_assert(2 * 2 * STAGE_DOUBLES * 8 <= 160 * 1024, "two workgroups per CU");
+  static_assert(TPC * NXU <= LDU && 3 * NP + TPC * NXU - NP <= LDW, "nodes past Np land in the pads");
+  static_assert(TPC == 16 && NP % 2 == 0 && LDU % 2 == 0 && LDW % 2 == 0, "16-byte pairs, rows of 16 lanes");
 };
+
+// The consumers' tiling of the [168 x 56] output (rows r = a Np + i, columns
+// j) without padding.  Two matrix instructions run at the same flop rate:
+// v_mfma_f64_16x16x4f64 (one 16 x 16 tile, lane i + 16k holds row i of A and
+// column i of B for k step k) and v_mfma_f64_4x4x4f64 (four 4 x 4 blocks b,
+// lane 16k + 4b + x holds row x of block b's A and column x of its B; the
+// result of row i, column j of block b is in lane 16i + 4b + j).  Four kinds
+// of products:
+//   F(rt, cb)  16 x 16 tile, rows 16rt.., columns 16cb..      (rt < 10, cb < 3)
+//   C(rt, cq)  16 x 4: block b = rows 16rt + 4b.., columns 4cq..  (cq = 12, 13)
+//   R(rq, cb)  4 x 16: block b = rows 4rq.., columns 16cb + 4b..  (rq = 40, 41)
+//   K          8 x 8: block b = rows 160 + 4(b >> 1).., columns 48 + 4(b & 1)..
+// A C product reads the same A register as F(rt, .) and an R product the same
+// B register as F(., cb), so the 168 x 56 outputs take 30 F + 20 C + 6 R + 1 K
+// products with no padding, where 16-wide tiles alone execute 1.20x the useful
+// products.  Consumer wave w < 3 takes F(0..8, w) and R(40, w) (592 matrix-core
+// cycles per k step, 64 per F product and 16 per small one); wave 3 takes the
+// C products, F(9, .), R(41, .) and K (576 cycles).
+//
+// Each product reads two operand slots (a slot is one row range of W or one
+// column range of u, of one lane layout).  A slot's value for k step kk is
+// read from LDS GD56_LEAD product cycles before its first use (at the start
+// of the step at the latest), so only the values in flight are live.
+struct Gd56Plan {
+  static constexpr int MAXOP = 28, MAXSLOT = 20, MAXRD = 4 * MAXSLOT, MAXPOS = 4 * MAXOP + 1;
+  int nop = 0, nslot = 0, nrd = 0;
+  int kind[MAXOP] = {};       // 0 F, 1 C, 2 R, 3 K
+  int p1[MAXOP] = {}, p2[MAXOP] = {};
+  int acc[MAXOP] = {};        // accumulator index within the kind's bank (F or small)
+  int sa[MAXOP] = {}, sb[MAXOP] = {};
+  int nfull = 0, nsmall = 0;
+  int stype[MAXSLOT] = {};    // lane layout: 0 A rows 16.., 1 B cols 16.., 2 A rows 4.., 3 B cols 4.., 4 A of K, 5 B of K
+  int soff[MAXSLOT] = {};     // first row or column of the slot
+  // reads in issue order: k step and slot; position = product index (over the
+  // step's KST k steps) before which the read is issued
+  int rd_kk[MAXRD] = {}, rd_slot[MAXRD] = {};
+  int rd_begin[MAXPOS + 1] = {};  // reads issued before product n: rd_begin[n] .. rd_begin[n + 1] - 1
+};
+
+constexpr int GD56_LEAD = 320;
+constexpr int gd56_cycles(int kind) { return kind == 0 ? 64 : 16; }
+
+constexpr int gd56_slot(Gd56Plan& P, int type, int off) {
+  for (int x = 0; x < P.nslot; ++x)
+    if (P.stype[x] == type && P.soff[x] == off) return x;
+  P.stype[P.nslot] = type;
+  P.soff[P.nslot] = off;
+  return P.nslot++;
+}
+
+constexpr void gd56_add(Gd56Plan& P, int kind, int p1, int p2) {
+  const int o = P.nop++;
+  P.kind[o] = kind;
+  P.p1[o] = p1;
+  P.p2[o] = p2;
+  P.acc[o] = kind == 0 ? P.nfull++ : P.nsmall++;
+  switch (kind) {
+    case 0: P.sa[o] = gd56_slot(P, 0, 16 * p1); P.sb[o] = gd56_slot(P, 1, 16 * p2); break;
+    case 1: P.sa[o] = gd56_slot(P, 0, 16 * p1); P.sb[o] = gd56_slot(P, 3, 4 * p2); break;
+    case 2: P.sa[o] = gd56_slot(P, 2, 4 * p1); P.sb[o] = gd56_slot(P, 1, 16 * p2); break;
+    default: P.sa[o] = gd56_slot(P, 4, 160); P.sb[o] = gd56_slot(P, 5, 48); break;
+  }
+}
+
+constexpr Gd56Plan gd56_plan(int wv, int kst) {
+  Gd56Plan P;
+  if (wv < 3) {
+    for (int rt = 0; rt < 9; ++rt) gd56_add(P, 0, rt, wv);
+    gd56_add(P, 2, 40, wv);
+  } else {
+    for (int rt = 0; rt < 10; ++rt) {
+      gd56_add(P, 1, rt, 12);
+      gd56_add(P, 1, rt, 13);
+      if (rt >= 7) {
+        gd56_add(P, 0, 9, rt - 7);
+        gd56_add(P, 2, 41, rt - 7);
+      }
+    }
+    gd56_add(P, 3, 0, 0);
+  }
+  // read schedule over the step's kst k steps (products n = kk * nop + o)
+  const int N = kst * P.nop;
+  int pos[Gd56Plan::MAXRD] = {}, first[Gd56Plan::MAXRD] = {};
+  for (int kk = 0; kk < kst; ++kk) {
+    for (int x = 0; x < P.nslot; ++x) {
+      int u = -1;
+      for (int o = 0; o < P.nop && u < 0; ++o)
+        if (P.sa[o] == x || P.sb[o] == x) u = kk * P.nop + o;
+      int n = u, cyc = 0;
+      while (n > 0 && cyc < GD56_LEAD) {
+        --n;
+        cyc += gd56_cycles(P.kind[n % P.nop]);
+      }
+      pos[P.nrd] = n;
+      first[P.nrd] = u;
+      P.rd_kk[P.nrd] = kk;
+      P.rd_slot[P.nrd] = x;
+      ++P.nrd;
+    }
+  }
+  // order by position, then by first use (insertion sort)
+  for (int i = 1; i < P.nrd; ++i)
+    for (int j = i; j > 0 && (pos[j - 1] > pos[j] || (pos[j - 1] == pos[j] && first[j - 1] > first[j])); --j) {
+      int t = pos[j]; pos[j] = pos[j - 1]; pos[j - 1] = t;
+      t = first[j]; first[j] = first[j - 1]; first[j - 1] = t;
+      t = P.rd_kk[j]; P.rd_kk[j] = P.rd_kk[j - 1]; P.rd_kk[j - 1] = t;
+      t = P.rd_slot[j]; P.rd_slot[j] = P.rd_slot[j - 1]; P.rd_slot[j - 1] = t;
+    }
+  int m = 0;
+  for (int n = 0; n <= N; ++n) {
+    P.rd_begin[n] = m;
+    while (m < P.nrd && pos[m] == n) ++m;
+  }
+  P.rd_begin[N + 1] = m;
+  return P;
+}
+
+template <int WV>
+struct Gd56Wave {
+  static constexpr Gd56Plan P = gd56_plan(WV, GdSplit56::KST);
+  static_assert(P.nop <= Gd56Plan::MAXOP && P.nslot <= Gd56Plan::MAXSLOT, "plan size");
+  static_assert(P.nrd == GdSplit56::KST * P.nslot, "every slot read once per k step");
+};
+
+template <int I, int N, typename Fn>
+__device__ __forceinline__ void gd_static_for(Fn& fn) {
+  if constexpr (I < N) {
+    fn(std::integral_constant<int, I>{});
+    gd_static_for<I + 1, N>(fn);
+  }
+}
+
+// One consumer wave: its products for every step of the range, then its part
+// of the partial sum.
+template <int WV>
+__device__ __forceinline__ void gd56_consume(const double* __restrict__ lds, uint32_t nsteps, double* __restrict__ w,
+                                             int lane) {
+  using S = GdSplit56;
+  using PW = Gd56Wave<WV>;
+  constexpr int NP = S::NP;
+  constexpr int NOP = PW::P.nop, NSLOT = PW::P.nslot, NFULL = PW::P.nfull, NSMALL = PW::P.nsmall;
+  constexpr int N = S::KST * NOP;
+  const int kq = lane >> 4;
+  // per-lane word offset of each slot layout within a staging buffer (k step 0)
+  const int lane_off[6] = {S::CH * S::LDU + kq * S::LDW + (lane & 15),
+                           kq * S::LDU + (lane & 15),
+                           S::CH * S::LDU + kq * S::LDW + (lane & 3),
+                           kq * S::LDU + (lane & 3),
+                           S::CH * S::LDU + kq * S::LDW + 4 * ((lane >> 3) & 1) + (lane & 3),
+                           kq * S::LDU + 4 * ((lane >> 2) & 1) + (lane & 3)};
+  f64x4 accf[NFULL > 0 ? NFULL : 1];
+  double accs[NSMALL > 0 ? NSMALL : 1];
+#pragma unroll
+  for (int t = 0; t < NFULL; ++t) accf[t] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int t = 0; t < NSMALL; ++t) accs[t] = 0.0;
+  __syncthreads();
+  for (uint32_t r = 0; r < nsteps; ++r) {
+    const double* buf = lds + (int)(r & 1u) * S::STAGE_DOUBLES;
+    double v[S::KST][NSLOT];
+    auto product = [&](auto nc) __attribute__((always_inline)) {
+      constexpr int n = decltype(nc)::value;
+      // the reads placed before product n (all of them, for n == N)
+      constexpr int rb = PW::P.rd_begin[n], re = PW::P.rd_begin[n + 1];
+      auto read = [&](auto ic) __attribute__((always_inline)) {
+        constexpr int m = rb + decltype(ic)::value;
+        constexpr int kk = PW::P.rd_kk[m], x = PW::P.rd_slot[m];
+        constexpr int ty = PW::P.stype[x];
+        constexpr int ld = (ty == 0 || ty == 2 || ty == 4) ? S::LDW : S::LDU;
+        v[kk][x] = buf[lane_off[ty] + 4 * kk * ld + PW::P.soff[x]];
+      };
+      gd_static_for<0, re - rb>(read);
+      if constexpr (re > rb) __builtin_amdgcn_sched_group_barrier(0x100, re - rb, 0);
+      if constexpr (n < N) {
+        constexpr int kk = n / NOP, o = n % NOP;
+        constexpr int a = PW::P.sa[o], b = PW::P.sb[o], t = PW::P.acc[o];
+        if constexpr (PW::P.kind[o] == 0)
+          accf[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(v[kk][a], v[kk][b], accf[t], 0, 0, 0);
+        else
+          accs[t] = __builtin_amdgcn_mfma_f64_4x4x4f64(v[kk][a], v[kk][b], accs[t], 0, 0, 0);
+        __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      }
+    };
+    gd_static_for<0, N + 1>(product);
+    __builtin_amdgcn_sched_barrier(0);
+    __syncthreads();  // the producers have staged step r + 1; buffer r % 2 is free
+  }
+  // partial sums: output row and column of each product's results
+#pragma unroll
+  for (int o = 0; o < NOP; ++o) {
+    const int kind = PW::P.kind[o], p1 = PW::P.p1[o], p2 = PW::P.p2[o], t = PW::P.acc[o];
+    const int b = (lane >> 2) & 3;
+    if (kind == 0) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) w[(int64_t)(16 * p1 + 4 * q + kq) * NP + 16 * p2 + (lane & 15)] = accf[t][q];
+    } else if (kind == 1) {
+      w[(int64_t)(16 * p1 + 4 * b + kq) * NP + 4 * p2 + (lane & 3)] = accs[t];
+    } else if (kind == 2) {
+      w[(int64_t)(4 * p1 + kq) * NP + 16 * p2 + (lane & 15)] = accs[t];
+    } else {
+      w[(int64_t)(160 + 4 * (b >> 1) + kq) * NP + 48 + 4 * (b & 1) + (lane & 3)] = accs[t];
+    }
+  }
+}
 
 __global__ __launch_bounds__(GdSplit56::NTH) __attribute__((amdgpu_waves_per_eu(4, 8)))
 void gd_split56_kernel(GdArgs p) {
@@ -281,7 +490,7 @@ void gd_split56_kernel(GdArgs p) {
   constexpr int NP = S::NP;
   constexpr int CH = S::CH;
   constexpr int SUB = GD_UNIT / CH;
-  __shared__ double lds[2 * S::STAGE_DOUBLES];
+  __shared__ __attribute__((aligned(16))) double lds[2 * S::STAGE_DOUBLES];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const uint32_t wave = __builtin_amdgcn_readfirstlane((uint32_t)tid >> 6);
@@ -291,9 +500,6 @@ void gd_split56_kernel(GdArgs p) {
   const uint32_t st_end = (uint32_t)((uint64_t)(part + 1) * p.nunits / p.npart) * SUB;
   const uint32_t nsteps = st_end - st_begin;
 
-  // pad entries (columns Np.. of u, rows 3 Np.. of W) stay zero
-  for (int x = tid; x < 2 * S::STAGE_DOUBLES; x += S::NTH) lds[x] = 0.0;
-  __syncthreads();
 
   const bool consumer = wave < S::NCONS;
   // ---- producer state: u and gout DEPTH steps ahead (register set r % DEPTH),
@@ -317,15 +523,27 @@ void gd_split56_kernel(GdArgs p) {
     const __amdgpu_buffer_rsrc_t b0 = buffer_range(p.gout + base, nb);
     const __amdgpu_buffer_rsrc_t b1 = buffer_range(p.gout + p.plane + base, nb);
     const __amdgpu_buffer_rsrc_t b2 = buffer_range(p.gout + 2 * p.plane + base, nb);
+    // nodes 2 (rr + 16 h) and the next one, as one 16-byte access per plane
 #pragma unroll
-    for (int q = 0; q < S::NXU; ++q) {
-      const uint32_t off = (uint32_t)(cc * NP + rr + S::TPC * q) * 8u;
-      ru[d][q] = buffer_load_f64(bu, off);
-      rg0[d][q] = buffer_load_f64(b0, off);
-      rg1[d][q] = buffer_load_f64(b1, off);
-      rg2[d][q] = buffer_load_f64(b2, off);
+    for (int h = 0; h < S::NPR; ++h) {
+      const uint32_t off = (uint32_t)(cc * NP + 2 * (rr + S::TPC * h)) * 8u;
+      const WordVec<double, 2> x = buffer_load_vec<double, 2>(bu, off);
+      const WordVec<double, 2> y0 = buffer_load_vec<double, 2>(b0, off);
+      const WordVec<double, 2> y1 = buffer_load_vec<double, 2>(b1, off);
+      const WordVec<double, 2> y2 = buffer_load_vec<double, 2>(b2, off);
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        ru[d][2 * h + e] = x.v[e];
+        rg0[d][2 * h + e] = y0.v[e];
+        rg1[d][2 * h + e] = y1.v[e];
+        rg2[d][2 * h + e] = y2.v[e];
+      }
     }
   };
+  // The 9 geometric factors of a column's element: lane rr of the column's
+  // 16-lane row loads factor rr, and a row broadcast (DPP) hands each factor
+  // to the whole row, instead of 16 lanes loading the same 72 bytes.
+  double gv = 0.0;
   auto load_g = [&](uint32_t r) __attribute__((always_inline)) {
     const uint32_t c0 = (st_begin + r) * CH;
     const uint32_t ncl = r < nsteps && c0 < p.ncols ? min((uint32_t)CH, p.ncols - c0) : 0u;
@@ -333,20 +551,38 @@ void gd_split56_kernel(GdArgs p) {
     const uint32_t nk = ncl ? (c0 + ncl - 1) / p.F - k0 + 1 : 0u;
     const __amdgpu_buffer_rsrc_t bg = buffer_range(p.G + (int64_t)k0 * 9, nk * 72u);
     const uint32_t ke = (c0 + (uint32_t)cc) / p.F - k0;  // this lane's element within the step
-#pragma unroll
-    for (int m = 0; m < 9; ++m) rG[m] = buffer_load_f64(bg, (ke * 9u + (uint32_t)m) * 8u);
+    gv = buffer_load_f64(bg, (ke * 9u + (uint32_t)min(rr, 8)) * 8u);
+  };
+  auto bcast_g = [&]() __attribute__((always_inline)) {
+    rG[0] = row_bcast_f64<0>(gv);
+    rG[1] = row_bcast_f64<1>(gv);
+    rG[2] = row_bcast_f64<2>(gv);
+    rG[3] = row_bcast_f64<3>(gv);
+    rG[4] = row_bcast_f64<4>(gv);
+    rG[5] = row_bcast_f64<5>(gv);
+    rG[6] = row_bcast_f64<6>(gv);
+    rG[7] = row_bcast_f64<7>(gv);
+    rG[8] = row_bcast_f64<8>(gv);
   };
   auto stage = [&](int d, int b) __attribute__((always_inline)) {
     double* ul = lds + b * S::STAGE_DOUBLES;
     double* wl = ul + CH * S::LDU;
+    bcast_g();
+    // A node past Np (the last pair of some threads) is written to the pads
+    // (u columns Np.., W rows 3 Np..), which no product reads: the writes need
+    // no branch, so the waits for the loads stay exact.
 #pragma unroll
-    for (int q = 0; q < S::NXU; ++q) {
-      const int i = rr + S::TPC * q;
-      if (i < NP) {
-        ul[cc * S::LDU + i] = ru[d][q];
+    for (int h = 0; h < S::NPR; ++h) {
+      const int i = 2 * (rr + S::TPC * h);
+      const bool in = i < NP;
+      *reinterpret_cast<f64x2*>(ul + cc * S::LDU + i) = f64x2{ru[d][2 * h], ru[d][2 * h + 1]};
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-          wl[cc * S::LDW + a * NP + i] = rG[3 * a] * rg0[d][q] + rG[3 * a + 1] * rg1[d][q] + rG[3 * a + 2] * rg2[d][q];
+      for (int a = 0; a < 3; ++a) {
+        f64x2 wv;
+#pragma unroll
+        for (int e = 0; e < 2; ++e)
+          wv[e] = rG[3 * a] * rg0[d][2 * h + e] + rG[3 * a + 1] * rg1[d][2 * h + e] + rG[3 * a + 2] * rg2[d][2 * h + e];
+        *reinterpret_cast<f64x2*>(wl + cc * S::LDW + (in ? a * NP + i : 3 * NP + i - NP)) = wv;
       }
     }
   };
@@ -355,55 +591,19 @@ void gd_split56_kernel(GdArgs p) {
   // one after the prologue, one per step.  Step r sits in producer register set
   // r % DEPTH and staging buffer r % 2 (DEPTH = 2: both alternate with r).
   if (consumer) {
-    // column block jb = wave, all row tiles
-    f64x4 acc[S::RT];
-#pragma unroll
-    for (int t = 0; t < S::RT; ++t) acc[t] = f64x4{0.0, 0.0, 0.0, 0.0};
-    const double* ub0 = lds + wave * 16 + (lane & 15);
-    const double* wa0 = lds + CH * S::LDU + (lane & 15);
-    __syncthreads();
-    for (uint32_t r = 0; r < nsteps; ++r) {
-      const int b = (int)(r & 1u);
-      const double* ub = ub0 + b * S::STAGE_DOUBLES;
-      const double* wa = wa0 + b * S::STAGE_DOUBLES;
-      // rolling operands: after each product the register of its A operand is
-      // refilled with the next k step's (one LDS read after each product)
-      const int cl = lane >> 4;
-      double av[S::RT];
-      double bv = ub[cl * S::LDU];
-#pragma unroll
-      for (int t = 0; t < S::RT; ++t) av[t] = wa[cl * S::LDW + t * 16];
-#pragma unroll
-      for (int kk = 0; kk < S::KST; ++kk) {
-        const int cn = 4 * (kk + 1) + cl;
-        const double bn = kk + 1 < S::KST ? ub[cn * S::LDU] : 0.0;
-#pragma unroll
-        for (int t = 0; t < S::RT; ++t) {
-          acc[t] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], bv, acc[t], 0, 0, 0);
-          if (kk + 1 < S::KST) av[t] = wa[cn * S::LDW + t * 16];
-        }
-#pragma unroll
-        for (int t = 0; t < S::RT; ++t) {
-          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // one product,
-          __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // then one LDS read
-        }
-        __builtin_amdgcn_sched_barrier(0);
-        bv = bn;
-      }
-      __syncthreads();  // the producers have staged step r + 1; buffer r % 2 is free
-    }
     double* w = p.work + (int64_t)part * 3 * NP * NP;
-    const int j = (int)wave * 16 + (lane & 15);
-#pragma unroll
-    for (int t = 0; t < S::RT; ++t) {
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = t * 16 + 4 * q + (lane >> 4);
-        if (r < 3 * NP && j < NP) w[(int64_t)r * NP + j] = acc[t][q];
-      }
+    switch (wave) {
+      case 0: gd56_consume<0>(lds, nsteps, w, lane); break;
+      case 1: gd56_consume<1>(lds, nsteps, w, lane); break;
+      case 2: gd56_consume<2>(lds, nsteps, w, lane); break;
+      default: gd56_consume<3>(lds, nsteps, w, lane); break;
     }
   } else {
     static_assert(S::DEPTH == 2, "register sets alternate with the step");
+    // The producers' vector work (FP64 multiply-adds, loads) shares the SIMDs
+    // with the consumers' matrix products, and every step waits for it at the
+    // barrier: issue it first (measured: 4 % faster).
+    __builtin_amdgcn_s_setprio(3);
     if (nsteps > 0) {
       load_ug(0, 0);
       load_ug(1, 1);
@@ -415,16 +615,17 @@ void gd_split56_kernel(GdArgs p) {
     __syncthreads();
     // iteration r stages step r + 1 (its G requested one iteration earlier, its u and
     // gout two), then requests G of step r + 2 and u, gout of step r + 3
+    // (nsteps is a whole number of partition units, so even: the pair of
+    // iterations needs no guard, and the waits for the loads stay exact)
+    static_assert(SUB % 2 == 0, "steps come in pairs");
     for (uint32_t r0 = 0; r0 < nsteps; r0 += 2) {
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
         const uint32_t r = r0 + j;
-        if (r < nsteps) {
-          stage(j ^ 1, j ^ 1);
-          load_g(r + 2);
-          load_ug(r + 3, j ^ 1);
-          __syncthreads();
-        }
+        stage(j ^ 1, j ^ 1);
+        load_g(r + 2);
+        load_ug(r + 3, j ^ 1);
+        __syncthreads();
       }
     }
   }
