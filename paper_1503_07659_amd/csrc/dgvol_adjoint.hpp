@@ -71,7 +71,10 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   __syncthreads();
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
-  const uint32_t wave = threadIdx.x >> 6;
+  // wave-uniform (readfirstlane): the tile index and the buffer descriptors built
+  // from it then live in scalar registers; a per-lane index makes the compiler
+  // wrap every buffer access in a loop over the distinct descriptors
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* stg = stg_all + wave * 16 * LD;
   double* red = red_all + wave * 16 * 9;
   double* gks = gks_all + wave * 16 * 9;  // geometric factors of the tile's (at most 16) elements
@@ -82,6 +85,21 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
     fo[r] = tswz(lane, r);
     tb[r] = (n >> 2) * WAVE + tswz(16 * (n & 3) + 4 * r + g, n >> 2);
   }
+  // The last 16-row tile of either product, when at most two of its row
+  // quads are real rows (slot quads of the forward product, output nodes of
+  // the transposed one), runs as one v_mfma_f64_4x4x4f64 per real quad r
+  // instead of one padded 16 x 16 product.  Block b of that instruction
+  // takes rows 4r.. and columns 4b.. of the tile: its A operand is row 4r + x
+  // of the tile's fragment (x = lane & 3, k = lane >> 4), its B operand is the
+  // 16 x 16 product's B register unchanged, and its result lands where
+  // component r of the 16 x 16 accumulator would.  Under the table's swizzle
+  // the A entry sits at a per-lane base (fs, ts) plus a constant 4 (r ^ s).
+  constexpr int FQ = Sh::SLOTS - 4 * (Sh::MT - 1);    // real row quads of the last forward tile
+  constexpr int JQ = (NP - 16 * (Sh::MTJ - 1) + 3) / 4;  // real row quads of the last transposed tile
+  constexpr bool FSPLIT = FQ <= 2, JSPLIT = JQ <= 2;
+  constexpr int MTJF = JSPLIT ? Sh::MTJ - 1 : Sh::MTJ;  // transposed tiles run as 16 x 16 products
+  const int fs = 16 * g + ((lane & 3) ^ g);
+  const int ts = 16 * (lane & 3) + (g ^ (lane & 3));
   const uint32_t stride = gridDim.x * WPB;
   uint32_t t = blockIdx.x * WPB + wave;
   // u of the tile and the geometric factors of its elements (one contiguous
@@ -187,8 +205,14 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
 #pragma unroll
         for (int tt = 0; tt < 3; ++tt) {
           const int T = 3 * ch + tt;
-          if (T < Sh::MT)
+          if (FSPLIT && T == Sh::MT - 1) {
+#pragma unroll
+            for (int r = 0; r < FQ; ++r)
+              acc[tt][r] = __builtin_amdgcn_mfma_f64_4x4x4f64(afr[(T * KS + s) * WAVE + fs + 4 * (r ^ (s & 3))], b,
+                                                              acc[tt][r], 0, 0, 0);
+          } else if (T < Sh::MT) {
             acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(afr[(T * KS + s) * WAVE + fo[s & 3]], b, acc[tt], 0, 0, 0);
+          }
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -225,10 +249,16 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
           wv[sl] = gl[3 * a] * go[x][0] + gl[3 * a + 1] * go[x][1] + gl[3 * a + 2] * go[x][2];
         }
       }
-      auto top = [&](int sp, int tj) { return afr[((sp >> 2) * KS + 4 * tj) * WAVE + tb[sp & 3]]; };
-      double tc[Sh::MTJ], tn[Sh::MTJ];
+      // operand o of slot sp: 16 x 16 tiles tj = o < MTJF, then the 4 x 4 quads of the last tile
+      constexpr int NJO = MTJF + (JSPLIT ? JQ : 0);
+      auto top = [&](int sp, int o) {
+        if (o < MTJF) return afr[((sp >> 2) * KS + 4 * o) * WAVE + tb[sp & 3]];
+        const int r = o - MTJF;
+        return afr[((sp >> 2) * KS + 4 * (Sh::MTJ - 1) + r) * WAVE + ts + 4 * ((sp & 3) ^ r)];
+      };
+      double tc[NJO], tn[NJO];
 #pragma unroll
-      for (int tj = 0; tj < Sh::MTJ; ++tj) tc[tj] = top(12 * ch, tj);
+      for (int o = 0; o < NJO; ++o) tc[o] = top(12 * ch, o);
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int sl = 0; sl < 12; ++sl) {
@@ -236,18 +266,23 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
         if (sp < Sh::SLOTS) {
           const bool more = sl + 1 < 12 && sp + 1 < Sh::SLOTS;
 #pragma unroll
-          for (int tj = 0; tj < Sh::MTJ; ++tj) {
-            if (more) tn[tj] = top(sp + 1, tj);
-            accj[tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(tc[tj], wv[sl], accj[tj], 0, 0, 0);
+          for (int o = 0; o < NJO; ++o) {
+            if (more) tn[o] = top(sp + 1, o);
+            if (o < MTJF) {
+              accj[o] = __builtin_amdgcn_mfma_f64_16x16x4f64(tc[o], wv[sl], accj[o], 0, 0, 0);
+            } else {
+              const int r = o - MTJF;
+              accj[Sh::MTJ - 1][r] = __builtin_amdgcn_mfma_f64_4x4x4f64(tc[o], wv[sl], accj[Sh::MTJ - 1][r], 0, 0, 0);
+            }
           }
 #pragma unroll
-          for (int tj = 0; tj < Sh::MTJ; ++tj) {
+          for (int o = 0; o < NJO; ++o) {
             __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
             __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
           }
           __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-          for (int tj = 0; tj < Sh::MTJ; ++tj) tc[tj] = tn[tj];
+          for (int o = 0; o < NJO; ++o) tc[o] = tn[o];
         }
       }
     }
