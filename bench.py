@@ -235,8 +235,7 @@ def mixed_orders(torch, dev):
                                  (dgvol.FORM_F32S, "f32s", torch.float32, 4)):
         trip = [tuple(torch.from_numpy(x).to(device=dev, dtype=dt) for x in host[N]) for N in sizes]
         outs = [torch.empty((3,) + tuple(t[2].shape), dtype=dt, device=dev) for t in trip]
-        ms_auto, _ = time_launches(lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs), 20, 3, torch,
-                                   min_warm_ms=WARM_MS)
+        default = lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs)  # noqa: E731
         ms_by_class, _ = time_launches(lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs, by_class=True),
                                        20, 3, torch, min_warm_ms=WARM_MS)
         # tuning (untimed): every variant of every order, then whole candidate plans on these groups
@@ -244,7 +243,13 @@ def mixed_orders(torch, dev):
         variants, costs, cand = plan.variants, plan.costs, plan.candidates
         tuned = lambda: dgvol.dg_volume_batched(trip, form=form, outs=outs, variants=variants,  # noqa: E731
                                                 costs=costs, by_class=plan.by_class)
-        ms_tuned, _ = time_launches(tuned, 20, 3, torch, min_warm_ms=WARM_MS)
+        # default and tuned plans timed in alternation (three rounds each, median), so that
+        # clock drift between them does not favour either
+        t_auto, t_tuned = [], []
+        for _ in range(3):
+            t_auto.append(time_launches(default, 10, 2, torch, min_warm_ms=WARM_MS / 2)[0])
+            t_tuned.append(time_launches(tuned, 10, 2, torch, min_warm_ms=WARM_MS / 2)[0])
+        ms_auto, ms_tuned = float(np.median(t_auto)), float(np.median(t_tuned))
         cap = CapturedLaunch(tuned)
         ms_graph, _ = time_launches(cap.replay, 20, 3, torch, min_warm_ms=WARM_MS)
         single = dgvol.dg_volume if form == dgvol.FORM_F64 else dgvol.dg_volume_f32s
@@ -260,6 +265,7 @@ def mixed_orders(torch, dev):
                      "tuned_ms": round(ms_tuned, 5), "default_ms": round(ms_auto, 5),
                      "default_by_class_ms": round(ms_by_class, 5),
                      "tuned_mode": "one launch per class" if plan.by_class else "one launch",
+                     "tuned_choice": min(cand, key=cand.get) if cand else None,
                      "one_launch_per_order_ms": round(ms_sep, 5), "roofline_ms": round(roof * 1e3, 5),
                      "frac_of_roofline": round(roof * 1e3 / ms_graph, 4),
                      "variants": {str(N): dict(dgvol.variant_info(form, setup_host.NODE_COUNTS[N],

@@ -173,6 +173,13 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
     const uint32_t col = col0 + (valid ? n : 0);
     const double* ge = gks + e * 9;  // geometric factors of this column's element
     const double* __restrict__ goc = gout + (int64_t)col * NP;
+    // (buffer form) the three gout planes of the tile's valid columns
+    static_assert(!BUF || NP == 4 * Sh::TRIP, "every node of a lane group is a real node");
+    __amdgpu_buffer_rsrc_t rgo[3];
+    if constexpr (BUF) {
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb) rgo[bb] = buffer_range(gout + bb * plane + (int64_t)col0 * NP, ncolt * NP * 8u);
+    }
     f64x4 accj[Sh::MTJ];
 #pragma unroll
     for (int tj = 0; tj < Sh::MTJ; ++tj) accj[tj] = f64x4{0.0, 0.0, 0.0, 0.0};
@@ -191,7 +198,12 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
       for (int x = 0; x < 4; ++x) {
         const int i = 4 * (4 * ch + x) + g;
 #pragma unroll
-        for (int bb = 0; bb < 3; ++bb) gor[x][bb] = 4 * ch + x < Sh::TRIP ? goc[bb * plane + min(i, NP - 1)] : 0.0;
+        for (int bb = 0; bb < 3; ++bb) {
+          if constexpr (BUF)  // columns past the tile read zero; i < Np (Np = 4 TRIP)
+            gor[x][bb] = 4 * ch + x < Sh::TRIP ? buffer_load_f64(rgo[bb], (uint32_t)(n * NP + i) * 8u) : 0.0;
+          else
+            gor[x][bb] = 4 * ch + x < Sh::TRIP ? goc[bb * plane + min(i, NP - 1)] : 0.0;
+        }
       }
       __builtin_amdgcn_sched_barrier(0);
       f64x4 acc[3];
@@ -219,7 +231,7 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
       double go[4][3];
 #pragma unroll
       for (int x = 0; x < 4; ++x) {
-        const bool ok = valid && 4 * (4 * ch + x) + g < NP;
+        const bool ok = BUF || (valid && 4 * (4 * ch + x) + g < NP);
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb) go[x][bb] = ok ? gor[x][bb] : 0.0;
       }
