@@ -11,10 +11,14 @@ namespace dgvol {
 
 // ------------------------------------------------------------------ adjoint FP64 (Np <= 56)
 //
-// Tiles are whole elements: E = 16 / F elements per 16-column tile when
-// F <= 16; when F > 16 a tile is one element, taken as ceil(F / 16) sub-tiles
-// of 16 columns in turn by the same wave.  Either way every element's gG sums
-// finish in one wave, in a fixed order, with no cross-wave reduction.  Per
+// F <= 16: each wave owns a contiguous run of whole elements and takes its
+// columns as full 16-column tiles (only the run's last tile can be short), so
+// no product column is idle (whole-element tiles left 1 of 16 idle at F = 3);
+// an element that straddles two tiles of the run carries its partial gG sum
+// into the next one.  F > 16: a tile is one element, taken as ceil(F / 16)
+// sub-tiles of 16 columns in turn by the same wave.  Either way every
+// element's gG sums finish in one wave, in a fixed order, with no cross-wave
+// reduction.  Per
 // (sub-)tile and chunk of 4 node triples: recompute R = D u (forward
 // fragments), read gout at the lane's nodes, accumulate gG partials, form
 // W = G^T gout lane-locally, then feed the 12 W slots straight in as the B
@@ -41,7 +45,7 @@ constexpr int adj_table_rows() {
 
 template <int NP, int WPB>
 constexpr int adj_staged_lds() {
-  return adj_table_rows<NP>() * WAVE * 8 + WPB * 16 * (NP + 1) * 8 + 2 * WPB * 16 * 9 * 8;
+  return adj_table_rows<NP>() * WAVE * 8 + WPB * 16 * (NP + 1) * 8 + 2 * WPB * 16 * 9 * 8 + WPB * 9 * 8;
 }
 
 // SUB = false: F <= 16, whole-element tiles of E = 16 / F elements; SUB = true:
@@ -51,7 +55,7 @@ template <int NP, int WPB, bool SUB>
 __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8))) void adj_f64_staged_kernel(
     const double* __restrict__ D, const double* __restrict__ G, const double* __restrict__ u,
     const double* __restrict__ gout, double* __restrict__ gu, double* __restrict__ gG, uint32_t K, uint32_t F,
-    int64_t plane, uint32_t E, uint32_t nsub, uint32_t ntiles) {
+    int64_t plane, uint32_t nsub, uint32_t ntiles) {
   using Sh = Shape<NP>;
   constexpr int KS = Sh::KS64;
   constexpr int NFRAG = fwd_table_doubles<NP>();
@@ -63,6 +67,7 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   __shared__ double stg_all[WPB * 16 * LD];
   __shared__ double red_all[WPB * 16 * 9];
   __shared__ double gks_all[WPB * 16 * 9];
+  __shared__ double cry_all[WPB * 9];  // partial gG of an element continued in the next tile
   static_assert(adj_staged_lds<NP, WPB>() <= 160 * 1024, "LDS budget");
   for (int e = threadIdx.x; e < NTAB; e += WAVE * WPB) {
     const int row = e >> 6, l = e & 63;
@@ -78,6 +83,7 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   double* stg = stg_all + wave * 16 * LD;
   double* red = red_all + wave * 16 * 9;
   double* gks = gks_all + wave * 16 * 9;  // geometric factors of the tile's (at most 16) elements
+  double* cry = cry_all + wave * 9;
   // per-lane LDS offsets: forward rows by s & 3, transposed rows by sp & 3
   int fo[4], tb[4];
 #pragma unroll
@@ -101,7 +107,36 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   const int fs = 16 * g + ((lane & 3) ^ g);
   const int ts = 16 * (lane & 3) + (g ^ (lane & 3));
   const uint32_t stride = gridDim.x * WPB;
-  uint32_t t = blockIdx.x * WPB + wave;
+  // F <= 16: this wave's run of elements [e_lo, e_hi), columns [c_lo, c_hi),
+  // tiles 0 .. nrun - 1 of 16 columns from c_lo.  F > 16: tiles t are elements,
+  // dealt to the waves in turn.
+  const uint32_t gw = blockIdx.x * WPB + wave;
+  const uint32_t e_lo = !SUB ? (uint32_t)((uint64_t)gw * K / stride) : 0u;
+  const uint32_t e_hi = !SUB ? (uint32_t)((uint64_t)(gw + 1) * K / stride) : 0u;
+  const uint32_t c_lo = e_lo * F, c_hi = e_hi * F;
+  const uint32_t nrun = !SUB ? (c_hi - c_lo + 15u) / 16u : 0u;
+  const uint32_t tend = !SUB ? nrun : ntiles;
+  uint32_t t = !SUB ? 0u : gw;
+  // first column, valid columns, first element and element count of tile tt
+  // (sub-tile ss when F > 16)
+  struct TileCols {
+    uint32_t col0, ncol, k0, ne;
+  };
+  auto tile_cols = [&](uint32_t tt, uint32_t ss) __attribute__((always_inline)) {
+    TileCols c;
+    if constexpr (!SUB) {
+      c.col0 = c_lo + 16u * tt;
+      c.ncol = tt < nrun ? min(16u, c_hi - c.col0) : 0u;
+      c.k0 = c.col0 / F;
+      c.ne = c.ncol ? (c.col0 + c.ncol - 1u) / F - c.k0 + 1u : 0u;
+    } else {
+      c.k0 = tt;
+      c.col0 = tt * F + 16u * ss;
+      c.ncol = tt < ntiles ? min(16u, F - 16u * ss) : 0u;
+      c.ne = tt < ntiles ? 1u : 0u;
+    }
+    return c;
+  };
   // u of the tile and the geometric factors of its elements (one contiguous
   // run of G), loaded one tile ahead
   constexpr int NGR = (16 * 9 + WAVE - 1) / WAVE;
@@ -115,35 +150,30 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   // the u run of sub-tile ss of tile tt (F <= 16: the whole tile, ss = 0; F > 16: one
   // element, columns 16 ss .. 16 ss + 15 of it) and the geometric factors of the tile
   auto load_raw = [&](uint32_t tt, uint32_t ss) __attribute__((always_inline)) {
-    const uint32_t kk0 = tt * E;
+    const TileCols tc = tile_cols(tt, ss);
     if constexpr (BUF) {
-      const bool any = tt < ntiles;
-      const uint32_t ne = any ? min(E, K - kk0) : 0u;
-      const uint32_t ucols = !SUB ? ne * F : (any ? min(16u, F - 16u * ss) : 0u);
-      const uint32_t ubase = kk0 * F + (!SUB ? 0u : 16u * ss);
-      const __amdgpu_buffer_rsrc_t ru = buffer_range(any ? u + (int64_t)ubase * NP : u, ucols * NP * 8u);
+      const bool any = tc.ncol > 0;
+      const __amdgpu_buffer_rsrc_t ru = buffer_range(any ? u + (int64_t)tc.col0 * NP : u, tc.ncol * NP * 8u);
 #pragma unroll
       for (int q = 0; q < NRAW; ++q) raw[q] = buffer_load_f64(ru, (uint32_t)(lane + WAVE * q) * 8u);
-      const __amdgpu_buffer_rsrc_t rg = buffer_range(any ? G + (int64_t)kk0 * 9 : G, ne * 9 * 8u);
+      const __amdgpu_buffer_rsrc_t rg = buffer_range(any ? G + (int64_t)tc.k0 * 9 : G, tc.ne * 9 * 8u);
 #pragma unroll
       for (int q = 0; q < NGR; ++q) graw[q] = buffer_load_f64(rg, (uint32_t)(lane + WAVE * q) * 8u);
     } else {
-      if (tt >= ntiles) return;
-      const uint32_t ne = min(E, K - kk0);
-      const uint32_t ucols = !SUB ? ne * F : min(16u, F - 16u * ss);
-      const double* __restrict__ src = u + (int64_t)(kk0 * F + (!SUB ? 0u : 16u * ss)) * NP;
-      const int cnt = (int)ucols * NP;
+      if (tc.ncol == 0) return;
+      const double* __restrict__ src = u + (int64_t)tc.col0 * NP;
+      const int cnt = (int)tc.ncol * NP;
 #pragma unroll
       for (int q = 0; q < NRAW; ++q) {
         const int x = lane + WAVE * q;
         const double v = src[min(x, cnt - 1)];
         raw[q] = x < cnt ? v : 0.0;
       }
-      const double* __restrict__ gsrc = G + (int64_t)kk0 * 9;
+      const double* __restrict__ gsrc = G + (int64_t)tc.k0 * 9;
 #pragma unroll
       for (int q = 0; q < NGR; ++q) {
         const int x = lane + WAVE * q;
-        graw[q] = x < (int)ne * 9 ? gsrc[x] : 0.0;
+        graw[q] = x < (int)tc.ne * 9 ? gsrc[x] : 0.0;
       }
     }
   };
@@ -151,12 +181,11 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   double P[9];
   uint32_t sub = 0;
   load_raw(t, 0);
-  while (t < ntiles) {
-    const uint32_t k0 = t * E;
-    const uint32_t ne = min(E, K - k0);
-    const uint32_t ncolt = !SUB ? ne * F : min(16u, F - 16u * sub);
+  const float invF = !SUB ? 1.0f / (float)F : 0.0f;
+  while (t < tend) {
+    const TileCols tcur = tile_cols(t, sub);
+    const uint32_t k0 = tcur.k0, ne = tcur.ne, ncolt = tcur.ncol, col0 = tcur.col0;
     const int cnt = (int)ncolt * NP;
-    const uint32_t col0 = k0 * F + (!SUB ? 0u : 16u * sub);
 #pragma unroll
     for (int q = 0; q < NRAW; ++q) {
       const int x = lane + WAVE * q;
@@ -169,7 +198,9 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
     }
     wave_sync();
     const bool valid = (uint32_t)n < ncolt;
-    const uint32_t e = (valid && !SUB) ? (uint32_t)n / F : 0u;
+    // element of this lane's column within the tile: (col0 mod F + n) / F, exact in
+    // float for these small integers (the + 0.5 keeps a whole quotient off its edge)
+    const uint32_t e = (valid && !SUB) ? (uint32_t)(((float)(col0 - k0 * F + (uint32_t)n) + 0.5f) * invF) : 0u;
     const uint32_t col = col0 + (valid ? n : 0);
     const double* ge = gks + e * 9;  // geometric factors of this column's element
     const double* __restrict__ goc = gout + (int64_t)col * NP;
@@ -340,12 +371,30 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
       }
       wave_sync();
       if constexpr (!SUB) {
-        if (g == 0 && (uint32_t)n < ne) {
+        // lane j < ne: element k0 + j, over its columns in this tile in order, after the
+        // partial sum carried from the previous tile when the element began there;
+        // written when it ends here, else carried into the next tile
+        const uint32_t ke = k0 + (uint32_t)n;
+        const bool mine = g == 0 && (uint32_t)n < ne;
+        const uint32_t cb = mine ? max(ke * F, col0) - col0 : 0u;
+        const uint32_t ce = mine ? min((ke + 1u) * F, col0 + ncolt) - col0 : 0u;
+        const bool from_prev = mine && n == 0 && ke * F < col0;
+        const bool ends = (ke + 1u) * F <= col0 + ncolt;
+        double sacc[9];
+#pragma unroll
+        for (int c = 0; c < 9; ++c) sacc[c] = from_prev ? cry[c] : 0.0;
+        for (uint32_t cc = cb; cc < ce; ++cc) {
+#pragma unroll
+          for (int c = 0; c < 9; ++c) sacc[c] += red[cc * 9 + c];
+        }
+        wave_sync();  // every lane has read the previous carry
+        if (mine) {
 #pragma unroll
           for (int c = 0; c < 9; ++c) {
-            double sacc = 0.0;
-            for (uint32_t f = 0; f < F; ++f) sacc += red[(n * F + f) * 9 + c];
-            gG[(int64_t)(k0 + n) * 9 + c] = sacc;
+            if (ends)
+              gG[(int64_t)ke * 9 + c] = sacc[c];
+            else
+              cry[c] = sacc[c];
           }
         }
       } else if (lane < 9) {
@@ -357,7 +406,7 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
       wave_sync();
     }
     if (last) {
-      t += stride;
+      t += !SUB ? 1u : stride;
       sub = 0;
     } else {
       ++sub;

@@ -249,6 +249,8 @@ struct AdjPlan {
   uint32_t resident[2];
   uint32_t units[2];     // work units of each kernel
   uint32_t workers[2];   // loop workers per workgroup (waves, or the workgroup itself)
+  uint32_t min_it[2];    // loop iterations of the least and the most loaded worker
+  uint32_t max_it[2];
 };
 
 template <int NP>
@@ -270,6 +272,8 @@ static dg_status adj_plan(int64_t K, int32_t F, AdjPlan* pl) {
       pl->resident[i] = (uint32_t)cap;
       pl->grid[i] = std::min<uint32_t>(pl->units[i], (uint32_t)cap);
       pl->workers[i] = 1;
+      pl->min_it[i] = pl->units[i] / pl->grid[i];
+      pl->max_it[i] = ceil_div(pl->units[i], pl->grid[i]);
     }
   } else {
     pl->nk = 1;
@@ -279,9 +283,23 @@ static dg_status adj_plan(int64_t K, int32_t F, AdjPlan* pl) {
     const int cap = resident_blocks_fn(pl->fn[0], pl->block, -1, &err);
     if (err != DG_OK) return err;
     pl->resident[0] = (uint32_t)cap;
-    pl->units[0] = ntiles;
-    pl->grid[0] = std::min<uint32_t>(ceil_div(ntiles, ADJ_WPB), (uint32_t)cap);
     pl->workers[0] = ADJ_WPB;
+    if (F <= 16) {
+      // runs of whole elements per wave, taken as 16-column tiles
+      const uint32_t tiles = ceil_div((uint64_t)K * (uint64_t)F, 16);
+      pl->units[0] = tiles;
+      pl->grid[0] = std::min<uint32_t>(ceil_div(tiles, ADJ_WPB), (uint32_t)cap);
+      const uint64_t nw = (uint64_t)pl->grid[0] * ADJ_WPB;
+      pl->min_it[0] = (uint32_t)ceil_div((uint64_t)(K / nw) * (uint64_t)F, 16);
+      pl->max_it[0] = (uint32_t)ceil_div(ceil_div((uint64_t)K, nw) * (uint64_t)F, 16);
+    } else {
+      // one element per tile, dealt to the waves in turn
+      pl->units[0] = (uint32_t)K;
+      pl->grid[0] = std::min<uint32_t>(ceil_div((uint64_t)K, ADJ_WPB), (uint32_t)cap);
+      const uint32_t nw = pl->grid[0] * ADJ_WPB;
+      pl->min_it[0] = pl->units[0] / nw;
+      pl->max_it[0] = ceil_div(pl->units[0], nw);
+    }
   }
   return DG_OK;
 }
@@ -305,10 +323,10 @@ static dg_status launch_adj_f64(const double* D, const double* G, const double* 
   } else {
     if (F <= 16)
       hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB, false>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D,
-                         G, u, gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
+                         G, u, gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, nsub, pl.units[0]);
     else
       hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB, true>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D,
-                         G, u, gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, E, nsub, ntiles);
+                         G, u, gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, nsub, pl.units[0]);
   }
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
@@ -691,9 +709,8 @@ dg_status dg_launch_shape_query(int32_t op, int32_t form, int32_t Np, int32_t va
     sh.min_iters = UINT32_MAX;
     sh.max_iters = 0;
     for (int i = 0; i < pl.nk; ++i) {
-      const uint32_t workers = pl.grid[i] * pl.workers[i];
-      sh.min_iters = std::min(sh.min_iters, pl.units[i] / workers);
-      sh.max_iters = std::max(sh.max_iters, ceil_div(pl.units[i], workers));
+      sh.min_iters = std::min(sh.min_iters, pl.min_it[i]);
+      sh.max_iters = std::max(sh.max_iters, pl.max_it[i]);
     }
   } else {
     return DG_EINVAL;

@@ -8,7 +8,8 @@
   library reports for the device (dg_launch_shape_query).
 * The adjoint at every order, F = 3 and F = 20 (below order 6: 16-column
   sub-tiles of each element; orders 6, 7: two-pass kernels), at three or more
-  loop iterations.
+  loop iterations; and every F up to 16 at orders 1, 4, 5, where runs of whole
+  elements are cut into full tiles and elements straddle tiles.
 * The mixed-order workload exactly as benchmarked (orders 1..7, group sizes
   from seed 3004, F = 3), both forms, with the default plan, the tuned plan
   and a graph replay of the tuned plan.
@@ -136,6 +137,32 @@ def test_adjoint_three_loop_iterations(N, F):
     c_gu, c_gG = adjoint_cond_c(D, G, u, gout)
     check_whole(host(gu), ref_gu, c_gu, what="gu")
     check_whole(host(gG), ref_gG, c_gG, what="gG")
+
+
+@pytest.mark.parametrize("N", [1, 4, 5])
+@pytest.mark.parametrize("F", [1, 2, 3, 5, 6, 7, 9, 11, 13, 15, 16])
+def test_adjoint_packed_tiles(N, F):
+    """F <= 16: each wave takes a run of whole elements as full 16-column tiles, so an
+    element can straddle two tiles and carry its partial gG into the next one.  Every F
+    up to 16 (each straddling pattern), at >= 3 tiles per wave, at an order with guarded
+    loads (1, 4) and one with buffer ranges (5): against the oracle, and the same bits
+    on a second run."""
+    Np = oracle.num_nodes(N)
+    K, sh = _k_for_iters(dgvol.OP_ADJOINT, dgvol.FORM_F64, Np, 0, F)
+    K += 5  # runs of unequal length
+    _say(f"adjoint packed tiles N={N} K={K} F={F} shape={sh}")
+    D = oracle.derivative_matrices(N)
+    G = oracle.geometric_factors(synth.tet_vertices(K, 5500 + N + F))
+    u = synth.fields(K, F, Np, 5600 + N + F, "uniform")
+    gout = synth.fields(K, 3 * F, Np, 5700 + N + F, "normal").reshape(K, 3, F, Np).transpose(1, 0, 2, 3).copy()
+    Dd, Gd, ud, gd = dev(D), dev(G), dev(u), dev(gout)
+    gu1, gG1 = (host(x).copy() for x in dgvol.dg_volume_adjoint(Dd, Gd, ud, gd))
+    gu2, gG2 = (host(x).copy() for x in dgvol.dg_volume_adjoint(Dd, Gd, ud, gd))
+    assert np.array_equal(gu1, gu2) and np.array_equal(gG1, gG2)
+    ref_gu, ref_gG = oracle.volume_adjoint(D, G, u, gout)
+    c_gu, c_gG = adjoint_cond_c(D, G, u, gout)
+    check_whole(gu1, ref_gu, c_gu, what="gu")
+    check_whole(gG1, ref_gG, c_gG, what="gG")
 
 
 # ------------------------------------------------------------------ the mixed-order workload as benchmarked
