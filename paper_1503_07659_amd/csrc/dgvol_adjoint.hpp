@@ -11,15 +11,13 @@ namespace dgvol {
 
 // ------------------------------------------------------------------ adjoint FP64 (Np <= 56)
 //
-// F <= 16: each wave owns a contiguous run of whole elements and takes its
-// columns as full 16-column tiles (only the run's last tile can be short), so
-// no product column is idle (whole-element tiles left 1 of 16 idle at F = 3);
-// an element that straddles two tiles of the run carries its partial gG sum
-// into the next one.  F > 16: a tile is one element, taken as ceil(F / 16)
-// sub-tiles of 16 columns in turn by the same wave.  Either way every
-// element's gG sums finish in one wave, in a fixed order, with no cross-wave
-// reduction.  Per
-// (sub-)tile and chunk of 4 node triples: recompute R = D u (forward
+// Each wave owns a contiguous run of whole elements and takes its columns as
+// full 16-column tiles (only the run's last tile can be short), so no product
+// column is idle: whole-element tiles left 1 of 16 columns idle at F = 3 and
+// 12 of 32 at F = 20.  An element that continues past a tile carries its
+// partial gG sum into the next one, so every element's gG sums finish in one
+// wave, in a fixed order, with no cross-wave reduction.  Per tile and chunk
+// of 4 node triples: recompute R = D u (forward
 // fragments), read gout at the lane's nodes, accumulate gG partials, form
 // W = G^T gout lane-locally, then feed the 12 W slots straight in as the B
 // operand of the transposed product D^T W (the slot order of W is the k order
@@ -48,14 +46,11 @@ constexpr int adj_staged_lds() {
   return adj_table_rows<NP>() * WAVE * 8 + WPB * 16 * (NP + 1) * 8 + 2 * WPB * 16 * 9 * 8 + WPB * 9 * 8;
 }
 
-// SUB = false: F <= 16, whole-element tiles of E = 16 / F elements; SUB = true:
-// F > 16, one element per tile in nsub sub-tiles (two instances, so that the
-// common case carries no sub-tile state).
-template <int NP, int WPB, bool SUB>
+template <int NP, int WPB>
 __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8))) void adj_f64_staged_kernel(
     const double* __restrict__ D, const double* __restrict__ G, const double* __restrict__ u,
     const double* __restrict__ gout, double* __restrict__ gu, double* __restrict__ gG, uint32_t K, uint32_t F,
-    int64_t plane, uint32_t nsub, uint32_t ntiles) {
+    int64_t plane) {
   using Sh = Shape<NP>;
   constexpr int KS = Sh::KS64;
   constexpr int NFRAG = fwd_table_doubles<NP>();
@@ -107,34 +102,24 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   const int fs = 16 * g + ((lane & 3) ^ g);
   const int ts = 16 * (lane & 3) + (g ^ (lane & 3));
   const uint32_t stride = gridDim.x * WPB;
-  // F <= 16: this wave's run of elements [e_lo, e_hi), columns [c_lo, c_hi),
-  // tiles 0 .. nrun - 1 of 16 columns from c_lo.  F > 16: tiles t are elements,
-  // dealt to the waves in turn.
+  // this wave's run of elements [e_lo, e_hi), columns [c_lo, c_hi), tiles
+  // 0 .. nrun - 1 of 16 columns from c_lo
   const uint32_t gw = blockIdx.x * WPB + wave;
-  const uint32_t e_lo = !SUB ? (uint32_t)((uint64_t)gw * K / stride) : 0u;
-  const uint32_t e_hi = !SUB ? (uint32_t)((uint64_t)(gw + 1) * K / stride) : 0u;
+  const uint32_t e_lo = (uint32_t)((uint64_t)gw * K / stride);
+  const uint32_t e_hi = (uint32_t)((uint64_t)(gw + 1) * K / stride);
   const uint32_t c_lo = e_lo * F, c_hi = e_hi * F;
-  const uint32_t nrun = !SUB ? (c_hi - c_lo + 15u) / 16u : 0u;
-  const uint32_t tend = !SUB ? nrun : ntiles;
-  uint32_t t = !SUB ? 0u : gw;
+  const uint32_t nrun = (c_hi - c_lo + 15u) / 16u;
+  uint32_t t = 0;
   // first column, valid columns, first element and element count of tile tt
-  // (sub-tile ss when F > 16)
   struct TileCols {
     uint32_t col0, ncol, k0, ne;
   };
-  auto tile_cols = [&](uint32_t tt, uint32_t ss) __attribute__((always_inline)) {
+  auto tile_cols = [&](uint32_t tt) __attribute__((always_inline)) {
     TileCols c;
-    if constexpr (!SUB) {
-      c.col0 = c_lo + 16u * tt;
-      c.ncol = tt < nrun ? min(16u, c_hi - c.col0) : 0u;
-      c.k0 = c.col0 / F;
-      c.ne = c.ncol ? (c.col0 + c.ncol - 1u) / F - c.k0 + 1u : 0u;
-    } else {
-      c.k0 = tt;
-      c.col0 = tt * F + 16u * ss;
-      c.ncol = tt < ntiles ? min(16u, F - 16u * ss) : 0u;
-      c.ne = tt < ntiles ? 1u : 0u;
-    }
+    c.col0 = c_lo + 16u * tt;
+    c.ncol = tt < nrun ? min(16u, c_hi - c.col0) : 0u;
+    c.k0 = c.col0 / F;
+    c.ne = c.ncol ? (c.col0 + c.ncol - 1u) / F - c.k0 + 1u : 0u;
     return c;
   };
   // u of the tile and the geometric factors of its elements (one contiguous
@@ -147,10 +132,9 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
   // compiler then allocates without spilling (measured -15 %).  At the lower
   // orders the guarded form measured 1-4 % faster.
   constexpr bool BUF = NP >= 56;
-  // the u run of sub-tile ss of tile tt (F <= 16: the whole tile, ss = 0; F > 16: one
-  // element, columns 16 ss .. 16 ss + 15 of it) and the geometric factors of the tile
-  auto load_raw = [&](uint32_t tt, uint32_t ss) __attribute__((always_inline)) {
-    const TileCols tc = tile_cols(tt, ss);
+  // the u run of tile tt and the geometric factors of its elements
+  auto load_raw = [&](uint32_t tt) __attribute__((always_inline)) {
+    const TileCols tc = tile_cols(tt);
     if constexpr (BUF) {
       const bool any = tc.ncol > 0;
       const __amdgpu_buffer_rsrc_t ru = buffer_range(any ? u + (int64_t)tc.col0 * NP : u, tc.ncol * NP * 8u);
@@ -177,13 +161,12 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
       }
     }
   };
-  // gG partial sums of the tile's columns, carried over its sub-tiles
+  // gG partial sums of the lane's column in the tile
   double P[9];
-  uint32_t sub = 0;
-  load_raw(t, 0);
-  const float invF = !SUB ? 1.0f / (float)F : 0.0f;
-  while (t < tend) {
-    const TileCols tcur = tile_cols(t, sub);
+  load_raw(t);
+  const float invF = 1.0f / (float)F;
+  while (t < nrun) {
+    const TileCols tcur = tile_cols(t);
     const uint32_t k0 = tcur.k0, ne = tcur.ne, ncolt = tcur.ncol, col0 = tcur.col0;
     const int cnt = (int)ncolt * NP;
 #pragma unroll
@@ -200,7 +183,7 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
     const bool valid = (uint32_t)n < ncolt;
     // element of this lane's column within the tile: (col0 mod F + n) / F, exact in
     // float for these small integers (the + 0.5 keeps a whole quotient off its edge)
-    const uint32_t e = (valid && !SUB) ? (uint32_t)(((float)(col0 - k0 * F + (uint32_t)n) + 0.5f) * invF) : 0u;
+    const uint32_t e = valid ? (uint32_t)(((float)(col0 - k0 * F + (uint32_t)n) + 0.5f) * invF) : 0u;
     const uint32_t col = col0 + (valid ? n : 0);
     const double* ge = gks + e * 9;  // geometric factors of this column's element
     const double* __restrict__ goc = gout + (int64_t)col * NP;
@@ -214,10 +197,8 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
     f64x4 accj[Sh::MTJ];
 #pragma unroll
     for (int tj = 0; tj < Sh::MTJ; ++tj) accj[tj] = f64x4{0.0, 0.0, 0.0, 0.0};
-    if (!SUB || sub == 0) {
 #pragma unroll
-      for (int c = 0; c < 9; ++c) P[c] = 0.0;
-    }
+    for (int c = 0; c < 9; ++c) P[c] = 0.0;
 #pragma unroll
     for (int ch = 0; ch < Sh::NCHUNK; ++ch) {
       // this lane's gout values for the chunk, requested before the forward
@@ -356,62 +337,50 @@ __global__ __launch_bounds__(WAVE* WPB) __attribute__((amdgpu_waves_per_eu(2, 8)
         if (x < cnt) gdst[x] = stg[(x / NP) * LD + (x % NP)];
       }
     }
-    // gG, after the tile's last sub-tile: four lane groups, then the F columns of each
-    // element, in a fixed order
-    const bool last = !SUB || sub + 1 >= nsub;
-    if (last) {
+    // gG: four lane groups, then the columns of each element, in a fixed order
 #pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        P[c] += __shfl_xor(P[c], 16);
-        P[c] += __shfl_xor(P[c], 32);
-      }
-      if (g == 0) {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) red[n * 9 + c] = P[c];
-      }
-      wave_sync();
-      if constexpr (!SUB) {
-        // lane j < ne: element k0 + j, over its columns in this tile in order, after the
-        // partial sum carried from the previous tile when the element began there;
-        // written when it ends here, else carried into the next tile
-        const uint32_t ke = k0 + (uint32_t)n;
-        const bool mine = g == 0 && (uint32_t)n < ne;
-        const uint32_t cb = mine ? max(ke * F, col0) - col0 : 0u;
-        const uint32_t ce = mine ? min((ke + 1u) * F, col0 + ncolt) - col0 : 0u;
-        const bool from_prev = mine && n == 0 && ke * F < col0;
-        const bool ends = (ke + 1u) * F <= col0 + ncolt;
-        double sacc[9];
-#pragma unroll
-        for (int c = 0; c < 9; ++c) sacc[c] = from_prev ? cry[c] : 0.0;
-        for (uint32_t cc = cb; cc < ce; ++cc) {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) sacc[c] += red[cc * 9 + c];
-        }
-        wave_sync();  // every lane has read the previous carry
-        if (mine) {
-#pragma unroll
-          for (int c = 0; c < 9; ++c) {
-            if (ends)
-              gG[(int64_t)ke * 9 + c] = sacc[c];
-            else
-              cry[c] = sacc[c];
-          }
-        }
-      } else if (lane < 9) {
-        // one element: its 16 lanes carry the partial sums of all its sub-tiles
-        double sacc = 0.0;
-        for (int m = 0; m < 16; ++m) sacc += red[m * 9 + lane];
-        gG[(int64_t)k0 * 9 + lane] = sacc;
-      }
-      wave_sync();
+    for (int c = 0; c < 9; ++c) {
+      P[c] += __shfl_xor(P[c], 16);
+      P[c] += __shfl_xor(P[c], 32);
     }
-    if (last) {
-      t += !SUB ? 1u : stride;
-      sub = 0;
-    } else {
-      ++sub;
+    if (g == 0) {
+#pragma unroll
+      for (int c = 0; c < 9; ++c) red[n * 9 + c] = P[c];
     }
-    load_raw(t, SUB ? sub : 0u);
+    wave_sync();
+    {
+      // lane j < ne: element k0 + j, over its columns in this tile in order, after the
+      // partial sum carried from the previous tile when the element began there;
+      // written when it ends here, else carried into the next tile (a tile that both
+      // takes and passes on a carry holds one element, lane 0: it reads the carry
+      // before the sync below and writes it after)
+      const uint32_t ke = k0 + (uint32_t)n;
+      const bool mine = g == 0 && (uint32_t)n < ne;
+      const uint32_t cb = mine ? max(ke * F, col0) - col0 : 0u;
+      const uint32_t ce = mine ? min((ke + 1u) * F, col0 + ncolt) - col0 : 0u;
+      const bool from_prev = mine && n == 0 && ke * F < col0;
+      const bool ends = (ke + 1u) * F <= col0 + ncolt;
+      double sacc[9];
+#pragma unroll
+      for (int c = 0; c < 9; ++c) sacc[c] = from_prev ? cry[c] : 0.0;
+      for (uint32_t cc = cb; cc < ce; ++cc) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) sacc[c] += red[cc * 9 + c];
+      }
+      wave_sync();  // every lane has read the previous carry
+      if (mine) {
+#pragma unroll
+        for (int c = 0; c < 9; ++c) {
+          if (ends)
+            gG[(int64_t)ke * 9 + c] = sacc[c];
+          else
+            cry[c] = sacc[c];
+        }
+      }
+    }
+    wave_sync();
+    ++t;
+    load_raw(t);
   }
 }
 

@@ -238,9 +238,9 @@ static double tile_cost_estimate(int form, int Np, uint32_t F) {
   return std::max(bytes / bw, flops / peak) / eff;
 }
 
-// Kernels and grids of the adjoint for (NP, K, F): one kernel (staged, or
-// general when F > 16) below Np = 84, two chunk-register passes (gu, then gG)
-// from Np = 84.
+// Kernels and grids of the adjoint for (NP, K, F): one staged kernel (runs of
+// whole elements per wave, any F) below Np = 84, two chunk-register passes
+// (gu, then gG) from Np = 84.
 struct AdjPlan {
   int nk;                // kernels launched
   const void* fn[2];
@@ -278,28 +278,18 @@ static dg_status adj_plan(int64_t K, int32_t F, AdjPlan* pl) {
   } else {
     pl->nk = 1;
     pl->block = WAVE * ADJ_WPB;
-    pl->fn[0] = F <= 16 ? reinterpret_cast<const void*>(adj_f64_staged_kernel<NP, ADJ_WPB, false>)
-                        : reinterpret_cast<const void*>(adj_f64_staged_kernel<NP, ADJ_WPB, true>);
+    pl->fn[0] = reinterpret_cast<const void*>(adj_f64_staged_kernel<NP, ADJ_WPB>);
     const int cap = resident_blocks_fn(pl->fn[0], pl->block, -1, &err);
     if (err != DG_OK) return err;
     pl->resident[0] = (uint32_t)cap;
     pl->workers[0] = ADJ_WPB;
-    if (F <= 16) {
-      // runs of whole elements per wave, taken as 16-column tiles
-      const uint32_t tiles = ceil_div((uint64_t)K * (uint64_t)F, 16);
-      pl->units[0] = tiles;
-      pl->grid[0] = std::min<uint32_t>(ceil_div(tiles, ADJ_WPB), (uint32_t)cap);
-      const uint64_t nw = (uint64_t)pl->grid[0] * ADJ_WPB;
-      pl->min_it[0] = (uint32_t)ceil_div((uint64_t)(K / nw) * (uint64_t)F, 16);
-      pl->max_it[0] = (uint32_t)ceil_div(ceil_div((uint64_t)K, nw) * (uint64_t)F, 16);
-    } else {
-      // one element per tile, dealt to the waves in turn
-      pl->units[0] = (uint32_t)K;
-      pl->grid[0] = std::min<uint32_t>(ceil_div((uint64_t)K, ADJ_WPB), (uint32_t)cap);
-      const uint32_t nw = pl->grid[0] * ADJ_WPB;
-      pl->min_it[0] = pl->units[0] / nw;
-      pl->max_it[0] = ceil_div(pl->units[0], nw);
-    }
+    // runs of whole elements per wave, taken as 16-column tiles
+    const uint32_t tiles = ceil_div((uint64_t)K * (uint64_t)F, 16);
+    pl->units[0] = tiles;
+    pl->grid[0] = std::min<uint32_t>(ceil_div(tiles, ADJ_WPB), (uint32_t)cap);
+    const uint64_t nw = (uint64_t)pl->grid[0] * ADJ_WPB;
+    pl->min_it[0] = (uint32_t)ceil_div((uint64_t)(K / nw) * (uint64_t)F, 16);
+    pl->max_it[0] = (uint32_t)ceil_div(ceil_div((uint64_t)K, nw) * (uint64_t)F, 16);
   }
   return DG_OK;
 }
@@ -321,12 +311,8 @@ static dg_status launch_adj_f64(const double* D, const double* G, const double* 
     hipLaunchKernelGGL(adjcr_gG_kernel<NP>, dim3(pl.grid[1]), dim3(pl.block), 0, stream, D, u, gout, gG, (uint32_t)K,
                        (uint32_t)F, (int64_t)ncols * NP, E, nsub, ntiles);
   } else {
-    if (F <= 16)
-      hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB, false>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D,
-                         G, u, gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, nsub, pl.units[0]);
-    else
-      hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB, true>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D,
-                         G, u, gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP, nsub, pl.units[0]);
+    hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D, G, u,
+                       gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP);
   }
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }

@@ -153,8 +153,8 @@ def test_adjoint_small(K, F):
 @pytest.mark.parametrize("N,F", [(3, 3), (5, 3), (6, 3), (7, 3), (3, 20), (5, 33)])
 def test_adjoint_guard_bands(N, F):
     """gu and gG are written only inside their views (order 5 stores gu through
-    buffer ranges that drop out-of-range lanes; orders 6-7 run two passes; F > 16
-    runs each element's fields as 16-column sub-tiles, the last one partial)."""
+    buffer ranges that drop out-of-range lanes; orders 6-7 run two passes; each
+    wave's last tile of a run, and elements with F > 16, leave partial tiles)."""
     K = 301
     Np = oracle.num_nodes(N)
     _say(f"adjoint guards N={N} K={K} F={F}")
@@ -175,7 +175,7 @@ def test_adjoint_guard_bands(N, F):
 
 @pytest.mark.parametrize("N,K,F", [(5, 3000, 3), (5, 700, 20), (6, 900, 3), (6, 250, 40), (7, 600, 3), (7, 300, 20)])
 def test_adjoint_deterministic(N, K, F):
-    """Every adjoint path (staged, general, two-pass) gives the same bits on
+    """Every adjoint path (staged runs, two-pass) gives the same bits on
     every run: gG is summed in a fixed order, with no atomics."""
     _say(f"adjoint determinism N={N} K={K} F={F}")
     D, G, u = make_case(N, K, F, 650 + N + F)

@@ -6,10 +6,10 @@
   iterations of its persistent loop, so the prefetch of the next tile and its
   staging are exercised; the size is derived from the launch shape the
   library reports for the device (dg_launch_shape_query).
-* The adjoint at every order, F = 3 and F = 20 (below order 6: 16-column
-  sub-tiles of each element; orders 6, 7: two-pass kernels), at three or more
-  loop iterations; and every F up to 16 at orders 1, 4, 5, where runs of whole
-  elements are cut into full tiles and elements straddle tiles.
+* The adjoint at every order, F = 3 and F = 20 (orders 6, 7: two-pass
+  kernels), at three or more loop iterations; and every F up to 16 plus
+  17, 20, 33, 40 at orders 1, 4, 5, where runs of whole elements are cut into
+  full tiles and elements straddle two or more tiles.
 * The mixed-order workload exactly as benchmarked (orders 1..7, group sizes
   from seed 3004, F = 3), both forms, with the default plan, the tuned plan
   and a graph replay of the tuned plan.
@@ -140,13 +140,14 @@ def test_adjoint_three_loop_iterations(N, F):
 
 
 @pytest.mark.parametrize("N", [1, 4, 5])
-@pytest.mark.parametrize("F", [1, 2, 3, 5, 6, 7, 9, 11, 13, 15, 16])
+@pytest.mark.parametrize("F", [1, 2, 3, 5, 6, 7, 9, 11, 13, 15, 16, 17, 20, 33, 40])
 def test_adjoint_packed_tiles(N, F):
-    """F <= 16: each wave takes a run of whole elements as full 16-column tiles, so an
-    element can straddle two tiles and carry its partial gG into the next one.  Every F
-    up to 16 (each straddling pattern), at >= 3 tiles per wave, at an order with guarded
-    loads (1, 4) and one with buffer ranges (5): against the oracle, and the same bits
-    on a second run."""
+    """Each wave takes a run of whole elements as full 16-column tiles, so an element
+    can straddle two tiles (F <= 16) or span three or more (F > 16, the middle ones
+    taking and passing on the carry) and carry its partial gG forward.  Every F up to
+    16 (each straddling pattern) and some above, at >= 3 tiles per wave, at an order
+    with guarded loads (1, 4) and one with buffer ranges (5): against the oracle, and
+    the same bits on a second run."""
     Np = oracle.num_nodes(N)
     K, sh = _k_for_iters(dgvol.OP_ADJOINT, dgvol.FORM_F64, Np, 0, F)
     K += 5  # runs of unequal length
