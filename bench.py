@@ -428,7 +428,9 @@ def summarize_mfma(root):
         frac = flops / (cycles * per_cycle)
         lds = ent.get("SQ_LDS_BANK_CONFLICT", 0.0) / max(ent.get("SQ_LDS_IDX_ACTIVE", 0.0), 1.0)
         dur = trace.get(key, float("nan"))
-        by_kernel.setdefault(name.split("(")[0], []).append((util, frac, lds, dur, flops))
+        # one kernel can serve two workloads (the adjoint at F = 3 and F = 20): one row per
+        # workload, told apart by the executed flops of a launch
+        by_kernel.setdefault((name.split("(")[0], round(flops / 1e9, 1)), []).append((util, frac, lds, dur, flops))
     os.makedirs(os.path.dirname(MFMA_FILE), exist_ok=True)
     with open(MFMA_FILE, "w") as fh:
         fh.write("# Matrix-core use of the FP64 kernels (rocprofv3 counters, MI355X)\n\n")
@@ -444,14 +446,15 @@ def summarize_mfma(root):
                  "(last column) run long; the bench line gives the warm times.\n")
         fh.write("* LDS conflict = SQ_LDS_BANK_CONFLICT / SQ_LDS_IDX_ACTIVE.\n")
         fh.write("* Workloads: order 4 K=2^20 F=5; order 5 K=2^19 F=3 (and the adjoint at K=2^16 F=20, the "
-                 "`true` instance); order 6 K=2^17 F=3; order 7 K=132228 F=3.\n\n")
+                 "same kernel: a row of its own, with its own flops per launch); order 6 K=2^17 F=3; "
+                 "order 7 K=132228 F=3.\n\n")
         fh.write("| kernel | dispatches | MFMA busy | executed of FP64 peak | executed GFLOP per launch | "
                  "LDS conflict | median ms (profiled) |\n")
         fh.write("|---|---|---|---|---|---|---|\n")
-        for name in sorted(by_kernel):
-            v = np.array(by_kernel[name])
+        for key in sorted(by_kernel):
+            v = np.array(by_kernel[key])
             med = np.median(v, axis=0)
-            fh.write(f"| `{name}` | {len(v)} | {med[0]:.3f} | {med[1]:.3f} | {med[4] / 1e9:.2f} | "
+            fh.write(f"| `{key[0]}` | {len(v)} | {med[0]:.3f} | {med[1]:.3f} | {med[4] / 1e9:.2f} | "
                      f"{med[2]:.3f} | {med[3] * 1e3:.4f} |\n")
     print(open(MFMA_FILE).read())
 
