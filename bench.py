@@ -265,7 +265,7 @@ def mixed_orders(torch, dev):
                      "tuned_ms": round(ms_tuned, 5), "default_ms": round(ms_auto, 5),
                      "default_by_class_ms": round(ms_by_class, 5),
                      "tuned_mode": "one launch per class" if plan.by_class else "one launch",
-                     "tuned_choice": min(cand, key=cand.get) if cand else None,
+                     "tuned_choice": plan_choice(cand),
                      "one_launch_per_order_ms": round(ms_sep, 5), "roofline_ms": round(roof * 1e3, 5),
                      "frac_of_roofline": round(roof * 1e3 / ms_graph, 4),
                      "variants": {str(N): dict(dgvol.variant_info(form, setup_host.NODE_COUNTS[N],
@@ -275,6 +275,17 @@ def mixed_orders(torch, dev):
         del trip, outs, cap
         torch.cuda.empty_cache()
     return res
+
+
+def plan_choice(cand):
+    """The candidate the batch tuner keeps: the fastest, unless the default is within its margin."""
+    from paper_1503_07659_amd import autotune
+    if not cand:
+        return None
+    best = min(cand, key=cand.get)
+    if "default" in cand and cand[best] > cand["default"] * (1.0 - autotune.PLAN_MARGIN):
+        best = "default"
+    return best
 
 
 def workload_inputs():

@@ -184,6 +184,10 @@ def plan(groups, form=dgvol.FORM_F64, tune_missing=True, by_class=False):
 BatchPlan = namedtuple("BatchPlan", "variants costs by_class candidates")
 
 
+# a tuned batch plan replaces the default launch only when it measures this much faster
+PLAN_MARGIN = 0.01
+
+
 def plan_batch(groups, form=dgvol.FORM_F64, outs=None, reps=10, tune_missing=True, save=True):
     """The fastest measured plan for this batch of groups, as a BatchPlan(variants, costs,
     by_class, candidates).
@@ -191,8 +195,9 @@ def plan_batch(groups, form=dgvol.FORM_F64, outs=None, reps=10, tune_missing=Tru
     Candidates, each in both launch modes (one launch for all 8-wave groups, and one launch per
     variant class): the library default (variant 0, estimated costs), the per-group tuned
     variants with their measured costs, and the tuned variants with the estimated costs.  Each
-    is timed on the actual groups; the result is cached under the batch's shapes.  candidates
-    maps each candidate's name to its measured seconds."""
+    is timed on the actual groups, in three alternating rounds; the default is kept unless a
+    candidate is more than PLAN_MARGIN faster.  The result is cached under the batch's shapes;
+    candidates maps each candidate's name to its measured seconds."""
     device = groups[0][2].device
     data = load_cache()
     key = batch_key(form, groups)
@@ -210,10 +215,19 @@ def plan_batch(groups, form=dgvol.FORM_F64, outs=None, reps=10, tune_missing=Tru
         cands["default" + suffix] = ([dgvol.VARIANT_AUTO] * n, [0.0] * n, bc)
         cands["tuned" + suffix] = (tv, tc, bc)
         cands["tuned_variants" + suffix] = (tv, [0.0] * n, bc)
-    times = {name: _median_time(lambda: dgvol.dg_volume_batched(groups, form=form, outs=outs, variants=v, costs=c,
-                                                                 by_class=bc), reps)
-             for name, (v, c, bc) in cands.items()}
+    # candidates timed in alternation (three rounds, median), so that clock drift does not
+    # favour the ones timed first
+    samples = {name: [] for name in cands}
+    for _ in range(3):
+        for name, (v, c, bc) in cands.items():
+            samples[name].append(_median_time(
+                lambda: dgvol.dg_volume_batched(groups, form=form, outs=outs, variants=v, costs=c, by_class=bc),
+                reps))
+    times = {name: float(np.median(s)) for name, s in samples.items()}
     best = min(times, key=times.get)
+    # the library default stays unless a candidate beats it by more than the timing noise
+    if times[best] > times["default"] * (1.0 - PLAN_MARGIN):
+        best = "default"
     v, c, bc = cands[best]
     ns[key] = {"variants": [int(x) for x in v], "costs": [float(x) for x in c], "by_class": bool(bc),
                "choice": best, "candidates_s": times}
