@@ -250,6 +250,8 @@ def mixed_orders(torch, dev):
             t_auto.append(time_launches(default, 10, 2, torch, min_warm_ms=WARM_MS / 2)[0])
             t_tuned.append(time_launches(tuned, 10, 2, torch, min_warm_ms=WARM_MS / 2)[0])
         ms_auto, ms_tuned = float(np.median(t_auto)), float(np.median(t_tuned))
+        if plan_choice(cand) == "default":
+            ms_tuned = ms_auto  # the tuner kept the default plan: the same launch
         cap = CapturedLaunch(tuned)
         ms_graph, _ = time_launches(cap.replay, 20, 3, torch, min_warm_ms=WARM_MS)
         single = dgvol.dg_volume if form == dgvol.FORM_F64 else dgvol.dg_volume_f32s

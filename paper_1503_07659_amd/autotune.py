@@ -33,6 +33,7 @@ rewritten.  Tuning needs a GPU; looking up the cache does not.
 import json
 import os
 import tempfile
+import time
 from collections import namedtuple
 
 import numpy as np
@@ -188,14 +189,14 @@ BatchPlan = namedtuple("BatchPlan", "variants costs by_class candidates")
 PLAN_MARGIN = 0.01
 
 
-def plan_batch(groups, form=dgvol.FORM_F64, outs=None, reps=10, tune_missing=True, save=True):
+def plan_batch(groups, form=dgvol.FORM_F64, outs=None, reps=20, tune_missing=True, save=True):
     """The fastest measured plan for this batch of groups, as a BatchPlan(variants, costs,
     by_class, candidates).
 
     Candidates, each in both launch modes (one launch for all 8-wave groups, and one launch per
     variant class): the library default (variant 0, estimated costs), the per-group tuned
     variants with their measured costs, and the tuned variants with the estimated costs.  Each
-    is timed on the actual groups, in three alternating rounds; the default is kept unless a
+    is timed on the actual groups, in five alternating rounds; the default is kept unless a
     candidate is more than PLAN_MARGIN faster.  The result is cached under the batch's shapes;
     candidates maps each candidate's name to its measured seconds."""
     device = groups[0][2].device
@@ -215,10 +216,15 @@ def plan_batch(groups, form=dgvol.FORM_F64, outs=None, reps=10, tune_missing=Tru
         cands["default" + suffix] = ([dgvol.VARIANT_AUTO] * n, [0.0] * n, bc)
         cands["tuned" + suffix] = (tv, tc, bc)
         cands["tuned_variants" + suffix] = (tv, [0.0] * n, bc)
-    # candidates timed in alternation (three rounds, median), so that clock drift does not
-    # favour the ones timed first
+    # candidates timed in alternation (five rounds, median) after the clocks have come up,
+    # so that clock drift does not favour the ones timed later
+    first = cands["default"]
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < 0.1:
+        dgvol.dg_volume_batched(groups, form=form, outs=outs, variants=first[0], costs=first[1], by_class=first[2])
+        torch.cuda.synchronize(device)
     samples = {name: [] for name in cands}
-    for _ in range(3):
+    for _ in range(5):
         for name, (v, c, bc) in cands.items():
             samples[name].append(_median_time(
                 lambda: dgvol.dg_volume_batched(groups, form=form, outs=outs, variants=v, costs=c, by_class=bc),

@@ -89,8 +89,8 @@ __device__ __forceinline__ void fwd_f64_staged_single(const FwdArgs<double>& p, 
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
   // wave-uniform (readfirstlane): branches on it are scalar (measured: order 4
-  // forward -0.7 %, split-BF16 -2.6 %; the chunk-register bodies and the two-pass
-  // adjoint measured slower with it)
+  // forward -0.7 %; the chunk-register bodies and the two-pass adjoint measured
+  // slower with it)
   const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double* stg = stg_all + wave * TILE;
   const uint32_t stride = nblk * WPB;

@@ -66,10 +66,7 @@ __device__ __forceinline__ void fwd_f32s_staged_single(const FwdArgs<float>& p, 
   const bool pairs = f32_pairs_ok(p);
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
-  // wave-uniform (readfirstlane): branches on it are scalar (measured: order 4
-  // forward -0.7 %, split-BF16 -2.6 %; the chunk-register bodies and the two-pass
-  // adjoint measured slower with it)
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wave = threadIdx.x >> 6;
   float* stg = stg_all + wave * TILE;
   const uint32_t stride = nblk * WPB;
   uint32_t t = bid * WPB + wave;
@@ -214,10 +211,7 @@ __device__ __forceinline__ void fwd_f32s_staged_multi(const FwdArgs<float>& p, u
   const bool pairs = f32_pairs_ok(p);
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
-  // wave-uniform (readfirstlane): branches on it are scalar (measured: order 4
-  // forward -0.7 %, split-BF16 -2.6 %; the chunk-register bodies and the two-pass
-  // adjoint measured slower with it)
-  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const uint32_t wave = threadIdx.x >> 6;
   float* su = reinterpret_cast<float*>(lds + 2 * NTE * 16) + wave * f32s_wave_floats<NP, TPI>();
   float* sg = su + RUN;
   const uint32_t nrun = (p.ntiles + TPI - 1) / TPI;
