@@ -532,6 +532,18 @@ def main():
     cal_flops = dgvol.MFMA_CAL_BLOCKS * 4 * 10000 * 4 * 2048
     mfma_tfs = cal_flops / (float(np.median(per_m)) * 1e-3) / 1e12
     del sink
+    # FP64 products beside vector work on the same SIMDs (20000 rounds of each): how much of
+    # the vector work overlaps the products
+    bsink = dgvol.dg_mfma_calibrate_beside(10, 10, dgvol.BESIDE_NONE)
+    beside = {}
+    for name, it, vit, mode in (("products_alone", 20000, 0, dgvol.BESIDE_NONE),
+                                ("fp64_fma_alone", 0, 20000, dgvol.BESIDE_FP64_FMA),
+                                ("products_beside_fp64_fma", 20000, 20000, dgvol.BESIDE_FP64_FMA),
+                                ("products_beside_int", 20000, 20000, dgvol.BESIDE_INT),
+                                ("products_beside_dpp", 20000, 20000, dgvol.BESIDE_DPP)):
+        _, per_b = time_launches(lambda: dgvol.dg_mfma_calibrate_beside(it, vit, mode, sink=bsink), 3, 1, torch)
+        beside[name] = round(float(np.median(per_b)), 4)
+    del bsink
 
     def step():
         dgvol.dg_volume(Dd, Gd, ud, out=out)
@@ -575,7 +587,8 @@ def main():
                      "frac_of_persistent_tile_stream": round(achieved / tile_gbs["persistent"], 4),
                      "fp64_tflops": round(flops_launch / (kern_ms * 1e-3) / 1e12, 2),
                      "fp64_frac": round(flops_launch / (kern_ms * 1e-3) / 1e12 / FP64_PEAK_TFS, 4),
-                     "measured_fp64_mfma_TFs": round(mfma_tfs, 2)},
+                     "measured_fp64_mfma_TFs": round(mfma_tfs, 2),
+                     "fp64_products_beside_vector_ms": beside},
     }
     del out
     torch.cuda.empty_cache()

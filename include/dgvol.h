@@ -59,7 +59,7 @@ typedef int32_t dg_status;
 #define DG_EDEVICE (-4)       /* querying the current device failed */
 #define DG_ESCRATCH (-5)      /* the problem needs more scratch than a fixed-scratch entry point holds */
 
-#define DGVOL_ABI_VERSION 3
+#define DGVOL_ABI_VERSION 4
 
 /* Forms (precisions) of the forward product. */
 #define DG_FORM_F64 0   /* FP64 storage, FP64 matrix cores */
@@ -348,6 +348,27 @@ dg_status dg_stream_calibrate_tiles(const double *src, double *dst, int64_t ntil
  */
 #define DG_MFMA_CAL_BLOCKS 2048
 dg_status dg_mfma_calibrate(double *sink, int32_t iters, void *stream);
+
+/*
+ * Calibration (not DG work): FP64 matrix products beside vector work on the
+ * same SIMDs.  DG_MFMA_BESIDE_BLOCKS workgroups of 512 threads (8 waves).
+ * Waves 0..3 run four independent chains of v_mfma_f64_16x16x4f64 for
+ * `iters` rounds, as dg_mfma_calibrate.  Waves 4..7, one per SIMD beside
+ * them, run `viters` rounds of 16 independent vector instructions of the kind
+ * `mode`: DG_BESIDE_NONE (nothing), DG_BESIDE_FP64_FMA (v_fma_f64),
+ * DG_BESIDE_INT (32-bit add, then xor), DG_BESIDE_DPP (row broadcast, then
+ * add).  With iters = 0 only the vector work runs.  Each thread writes one
+ * double to sink[0 .. DG_MFMA_BESIDE_BLOCKS * 512).
+ * Source: defined by this library (a measurement of the chip, not DG work).
+ * Errors: DG_EINVAL (null or misaligned sink, iters < 0, viters < 0, both
+ *         zero, unknown mode), DG_ELAUNCH.
+ */
+#define DG_MFMA_BESIDE_BLOCKS 256
+#define DG_BESIDE_NONE 0
+#define DG_BESIDE_FP64_FMA 1
+#define DG_BESIDE_INT 2
+#define DG_BESIDE_DPP 3
+dg_status dg_mfma_calibrate_beside(double *sink, int32_t iters, int32_t viters, int32_t mode, void *stream);
 
 #ifdef __cplusplus
 }

@@ -157,4 +157,65 @@ __global__ __launch_bounds__(1024) void mfma_cal_kernel(double* __restrict__ sin
   sink[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
 }
 
+// ------------------------------------------------------------------ products beside vector work
+//
+// One 8-wave workgroup per CU.  Waves 0..3 (one per SIMD) run the four chains
+// of mfma_cal_kernel for `iters` rounds; waves 4..7 (one per SIMD, beside
+// them) run `viters` rounds of 16 independent vector instructions of one kind:
+//   MODE 0 nothing, 1 v_fma_f64, 2 32-bit integer add then xor, 3 a DPP row
+//   broadcast (row_newbcast) then an add.
+// With iters = 0 only the vector work runs.  Comparing the times shows how
+// much of the vector work overlaps the FP64 products on the same SIMD.
+template <int MODE>
+__global__ __launch_bounds__(1024) void mfma_beside_kernel(double* __restrict__ sink, int32_t iters,
+                                                           int32_t viters) {
+  const int lane = threadIdx.x & 63;
+  const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double s = 0.0;
+  if (wave < 4) {
+    const double a = 1.0 + 1e-3 * lane, b = 1.0 - 1e-3 * lane;
+    f64x4 c0 = f64x4{0.0, 0.0, 0.0, 0.0}, c1 = c0, c2 = c0, c3 = c0;
+    for (int32_t it = 0; it < iters; ++it) {
+      c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c0, 0, 0, 0);
+      c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, a, c1, 0, 0, 0);
+      c2 = __builtin_amdgcn_mfma_f64_16x16x4f64(a, a, c2, 0, 0, 0);
+      c3 = __builtin_amdgcn_mfma_f64_16x16x4f64(b, b, c3, 0, 0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) s += c0[q] + c1[q] + c2[q] + c3[q];
+  } else if constexpr (MODE == 1) {
+    double x[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = 1.0 + 1e-4 * (lane + t);
+    for (int32_t it = 0; it < viters; ++it) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) x[t] = __builtin_fma(x[t], 0.999999, 1e-7);
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) s += x[t];
+  } else if constexpr (MODE == 2) {
+    uint32_t x[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = (uint32_t)(lane + t);
+    const uint32_t inc = (uint32_t)viters | 1u;
+    for (int32_t it = 0; it < viters; ++it) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) x[t] = (x[t] + inc) ^ (uint32_t)t;
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) s += (double)x[t];
+  } else if constexpr (MODE == 3) {
+    int x[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = lane * 16 + t;
+    for (int32_t it = 0; it < viters; ++it) {
+#pragma unroll
+      for (int t = 0; t < 16; ++t) x[t] = __builtin_amdgcn_mov_dpp(x[t], 0x153, 0xf, 0xf, false) + t;
+    }
+#pragma unroll
+    for (int t = 0; t < 16; ++t) s += (double)x[t];
+  }
+  sink[(int64_t)blockIdx.x * blockDim.x + threadIdx.x] = s;
+}
+
 }  // namespace dgvol

@@ -766,4 +766,18 @@ dg_status dg_mfma_calibrate(double* sink, int32_t iters, void* stream) {
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
 }
 
+dg_status dg_mfma_calibrate_beside(double* sink, int32_t iters, int32_t viters, int32_t mode, void* stream) {
+  if (!sink || !aligned(sink, 8) || iters < 0 || viters < 0 || iters + (int64_t)viters < 1) return DG_EINVAL;
+  const dim3 grid(DG_MFMA_BESIDE_BLOCKS), block(512);
+  const hipStream_t s = (hipStream_t)stream;
+  switch (mode) {
+    case DG_BESIDE_NONE: hipLaunchKernelGGL(mfma_beside_kernel<0>, grid, block, 0, s, sink, iters, viters); break;
+    case DG_BESIDE_FP64_FMA: hipLaunchKernelGGL(mfma_beside_kernel<1>, grid, block, 0, s, sink, iters, viters); break;
+    case DG_BESIDE_INT: hipLaunchKernelGGL(mfma_beside_kernel<2>, grid, block, 0, s, sink, iters, viters); break;
+    case DG_BESIDE_DPP: hipLaunchKernelGGL(mfma_beside_kernel<3>, grid, block, 0, s, sink, iters, viters); break;
+    default: return DG_EINVAL;
+  }
+  return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
+}
+
 }  // extern "C"

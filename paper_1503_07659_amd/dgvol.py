@@ -113,6 +113,8 @@ def load_library(path=None):
     lib.dg_stream_calibrate_tiles.restype = I32
     lib.dg_mfma_calibrate.argtypes = [P, I32, P]
     lib.dg_mfma_calibrate.restype = I32
+    lib.dg_mfma_calibrate_beside.argtypes = [P, I32, I32, I32, P]
+    lib.dg_mfma_calibrate_beside.restype = I32
     lib.dg_volume_batched.argtypes = [ctypes.POINTER(DgGroup), I32, I32, I32, P]
     lib.dg_volume_batched.restype = I32
     lib.dg_variant_count.argtypes = [I32, I32]
@@ -400,6 +402,24 @@ def dg_mfma_calibrate(iters, sink=None):
         st = load_library().dg_mfma_calibrate(sink.data_ptr(), int(iters), _stream_handle(sink.device))
     _raise_on(st, "dg_mfma_calibrate")
     return sink, MFMA_CAL_BLOCKS * 4 * int(iters) * 4 * 2048
+
+
+MFMA_BESIDE_BLOCKS = 256
+BESIDE_NONE, BESIDE_FP64_FMA, BESIDE_INT, BESIDE_DPP = 0, 1, 2, 3
+
+
+def dg_mfma_calibrate_beside(iters, viters, mode, sink=None):
+    """FP64 matrix products (waves 0..3 of each workgroup) beside `viters` rounds of 16 vector
+    instructions of kind `mode` (waves 4..7, the same SIMDs); returns the sink."""
+    dev = torch.device("cuda", torch.cuda.current_device())
+    if sink is None:
+        sink = torch.empty(MFMA_BESIDE_BLOCKS * 512, dtype=torch.float64, device=dev)
+    _check_tensor("sink", sink, torch.float64, (MFMA_BESIDE_BLOCKS * 512,))
+    with torch.cuda.device(sink.device):
+        st = load_library().dg_mfma_calibrate_beside(sink.data_ptr(), int(iters), int(viters), int(mode),
+                                                     _stream_handle(sink.device))
+    _raise_on(st, "dg_mfma_calibrate_beside")
+    return sink
 
 
 class DGVolume(torch.autograd.Function):

@@ -43,7 +43,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_version_and_strerror(lib):
-    assert lib.dg_abi_version() == 3
+    assert lib.dg_abi_version() == 4
     for st in (0, -1, -2, -3, -4, -5, -99):
         msg = lib.dg_strerror(st)
         assert isinstance(msg, bytes) and msg
@@ -163,6 +163,14 @@ def test_mfma_calibrate_validation(lib):
     assert lib.dg_mfma_calibrate(None, 10, None) == dgvol.DG_EINVAL
     assert lib.dg_mfma_calibrate(FAKE + 4, 10, None) == dgvol.DG_EINVAL
     assert lib.dg_mfma_calibrate(FAKE, 0, None) == dgvol.DG_EINVAL
+    # products beside vector work: sink, counts and mode are validated before any launch
+    assert lib.dg_mfma_calibrate_beside(None, 10, 10, dgvol.BESIDE_FP64_FMA, None) == dgvol.DG_EINVAL
+    assert lib.dg_mfma_calibrate_beside(FAKE + 4, 10, 10, dgvol.BESIDE_FP64_FMA, None) == dgvol.DG_EINVAL
+    assert lib.dg_mfma_calibrate_beside(FAKE, -1, 10, dgvol.BESIDE_FP64_FMA, None) == dgvol.DG_EINVAL
+    assert lib.dg_mfma_calibrate_beside(FAKE, 10, -1, dgvol.BESIDE_FP64_FMA, None) == dgvol.DG_EINVAL
+    assert lib.dg_mfma_calibrate_beside(FAKE, 0, 0, dgvol.BESIDE_FP64_FMA, None) == dgvol.DG_EINVAL
+    assert lib.dg_mfma_calibrate_beside(FAKE, 10, 10, 4, None) == dgvol.DG_EINVAL
+    assert lib.dg_mfma_calibrate_beside(FAKE, 10, 10, -1, None) == dgvol.DG_EINVAL
 
 
 def test_python_binding_rejects_cpu_tensors():

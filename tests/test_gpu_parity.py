@@ -475,6 +475,31 @@ def test_mfma_calibrate():
     assert 20.0 < tflops < 90.0, tflops
 
 
+@pytest.mark.parametrize("mode", [dgvol.BESIDE_NONE, dgvol.BESIDE_FP64_FMA, dgvol.BESIDE_INT, dgvol.BESIDE_DPP])
+def test_mfma_calibrate_beside(mode):
+    """Products beside vector work: every mode runs (products and vector work, or either alone)
+    and writes every sink entry; the mode with nothing beside the products gives the
+    calibration's own per-lane sums."""
+    _say(f"mfma beside mode={mode}")
+    n = dgvol.MFMA_BESIDE_BLOCKS * 512
+    for iters, viters in ((10, 10), (0, 10), (10, 0)):
+        if mode == dgvol.BESIDE_NONE and iters == 0:
+            continue
+        sink = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        dgvol.dg_mfma_calibrate_beside(iters, viters, mode, sink=sink)
+        torch.cuda.synchronize()
+        assert torch.isfinite(sink).all()
+    if mode == dgvol.BESIDE_NONE:
+        ref = torch.full((dgvol.MFMA_CAL_BLOCKS * 256,), float("nan"), dtype=torch.float64, device="cuda")
+        dgvol.dg_mfma_calibrate(10, sink=ref)
+        sink = torch.full((n,), float("nan"), dtype=torch.float64, device="cuda")
+        dgvol.dg_mfma_calibrate_beside(10, 0, mode, sink=sink)
+        torch.cuda.synchronize()
+        # waves 0..3 of each workgroup run the same chains as the calibration's waves
+        assert torch.equal(sink.view(-1, 512)[:, :256], ref.view(-1, 256)[: dgvol.MFMA_BESIDE_BLOCKS])
+        assert (sink.view(-1, 512)[:, 256:] == 0.0).all()
+
+
 def _mixed_case(sizes, F, form, seed):
     D, G, u = {}, {}, {}
     for N, K in sizes.items():
