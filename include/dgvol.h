@@ -276,11 +276,10 @@ dg_status dg_volume_variant(int32_t form, int32_t variant, const void *D, const 
  * without launching anything (it queries the device's occupancy for the
  * kernel).  A work unit is a 16-column tile.  The forward loops hand out
  * tiles round-robin; below Np = 84 the adjoint gives each wave a run of whole
- * elements, taken as 16-column tiles (at Np = 84, 120 its second pass takes
- * tiles of whole elements, 16/F of them, or one element in ceil(F/16)
- * sub-tiles).  min_iters is the loop iterations of the least-loaded wave (or
- * workgroup, for the workgroup-wide loops), taken over every kernel the
- * operation launches.
+ * elements, taken as 16-column tiles (at Np = 84, 120 its second pass gives
+ * such a run to each workgroup).  min_iters is the loop iterations of the
+ * least-loaded wave (or workgroup, for the workgroup-wide loops), taken over
+ * every kernel the operation launches.
  */
 typedef struct dg_launch_shape {
   uint32_t grid;            /* workgroups launched (first kernel of the operation) */

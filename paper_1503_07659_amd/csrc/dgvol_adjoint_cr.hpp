@@ -20,11 +20,13 @@
 //     Wave w < NCH keeps the A operands of output chunk w (3 tiles, as the
 //     forward chunk-register body, or 2 at Np = 84 so that all 8 waves work),
 //     recomputes D u for the chunk's slots from u staged in LDS, and reduces
-//     it with gout at its lanes' nodes (at most 4 node triples).  Tiles are
-//     whole elements (16/F of them, or one element in ceil(F/16) sub-tiles when
-//     F > 16) so every element's sums finish inside one workgroup; the partial
-//     sums are added in a fixed order (lane groups, then sub-tiles, then
-//     waves, then the element's columns), so gG is reproducible bit for bit.
+//     it with gout at its lanes' nodes (at most 4 node triples).  Each
+//     workgroup owns a run of whole elements and takes its columns as full
+//     16-column tiles (whole-element tiles left 1 of 16 columns idle at F = 3);
+//     an element that continues past a tile carries its partial sum into the
+//     next one, so every element's sums finish inside one workgroup.  The
+//     partial sums are added in a fixed order (lane groups, then waves, then
+//     the element's columns in order), so gG is reproducible bit for bit.
 //
 // gout is read twice (once per pass), u once; the matrix work equals the
 // single-pass adjoint's.
@@ -234,12 +236,12 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
                                                                   const double* __restrict__ u,
                                                                   const double* __restrict__ gout,
                                                                   double* __restrict__ gG, uint32_t K, uint32_t F,
-                                                                  int64_t plane, uint32_t E, uint32_t nsub,
-                                                                  uint32_t ntiles) {
+                                                                  int64_t plane) {
   using Sh = Shape<NP>;
   using S = AdjCrB<NP>;
   __shared__ double us[16 * S::LD];
-  __shared__ double red[ADJCR_WPB][16][9];  // per wave and column, summed over sub-tiles
+  __shared__ double red[ADJCR_WPB][16][9];  // per wave and column
+  __shared__ double cry[2][9];  // partial gG of an element continued in the next tile (slot by tile parity)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int n = lane & 15, g = lane >> 4;
@@ -262,39 +264,36 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
         atl[(w * S::KL + s - S::KR) * WAVE + lane] = a;  // read back by this lane only
     }
   }
-  // columns of tile t (whole elements) and of its sub-tile `sub`
-  auto tile_cols = [&](uint32_t tt) __attribute__((always_inline)) {
-    const uint32_t ne = min(E, K - tt * E);
-    return F <= 16 ? ne * F : F;
-  };
+  // this workgroup's run of elements [e_lo, e_hi), columns [c_lo, c_hi),
+  // tiles 0 .. nrun - 1 of 16 columns from c_lo
+  const uint32_t e_lo = (uint32_t)((uint64_t)blockIdx.x * K / gridDim.x);
+  const uint32_t e_hi = (uint32_t)((uint64_t)(blockIdx.x + 1) * K / gridDim.x);
+  const uint32_t c_lo = e_lo * F, c_hi = e_hi * F;
+  const uint32_t nrun = (c_hi - c_lo + 15u) / 16u;
   double ur[S::NLD];
   // u and gout move through buffer ranges (32-bit offsets, zero past the
   // range, empty past the last tile), which frees the address registers of
   // the clamped 64-bit form
-  auto load = [&](uint32_t tt, uint32_t sub) __attribute__((always_inline)) {
-    const bool any = tt < ntiles;
-    const uint32_t c0 = any ? tt * E * F + 16 * sub : 0u;
-    const uint32_t cnt = any ? min(16u, tile_cols(tt) - 16 * sub) * NP : 0u;
+  auto load = [&](uint32_t tt) __attribute__((always_inline)) {
+    const bool any = tt < nrun;
+    const uint32_t c0 = any ? c_lo + 16u * tt : 0u;
+    const uint32_t cnt = any ? min(16u, c_hi - c0) * NP : 0u;
     const __amdgpu_buffer_rsrc_t ru = buffer_range(u + (int64_t)c0 * NP, cnt * 8u);
 #pragma unroll
     for (int q = 0; q < S::NLD; ++q) ur[q] = buffer_load_f64(ru, (uint32_t)(tid + S::NTH * q) * 8u);
   };
-  uint32_t t = blockIdx.x, sub = 0;
-  load(t, 0);
-  while (t < ntiles) {
-    const uint32_t ncolt = tile_cols(t);
-    const uint32_t c0 = t * E * F + 16 * sub;
-    const uint32_t nc = min(16u, ncolt - 16 * sub);  // valid columns of this sub-tile
+  uint32_t t = 0;
+  load(t);
+  while (t < nrun) {
+    const uint32_t c0 = c_lo + 16u * t;
+    const uint32_t nc = min(16u, c_hi - c0);  // valid columns of this tile
 #pragma unroll
     for (int q = 0; q < S::NLD; ++q) {
       const int x = tid + S::NTH * q;
       if (x < 16 * NP) us[(x / NP) * S::LD + (x % NP)] = ur[q];
     }
     __syncthreads();
-    const bool last = sub + 1 == nsub;
-    const uint32_t t_next = last ? t + gridDim.x : t;
-    const uint32_t sub_next = last ? 0u : sub + 1;
-    load(t_next, sub_next);
+    load(t + 1);
     if (mma) {
       // this lane's gout values, requested before the products (clamped
       // addresses: unconditional loads; entries outside are zeroed)
@@ -363,29 +362,36 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
       }
       if (g == 0) {
 #pragma unroll
-        for (int c = 0; c < 9; ++c) red[w][n][c] = (sub == 0 ? 0.0 : red[w][n][c]) + P[c];
+        for (int c = 0; c < 9; ++c) red[w][n][c] = P[c];
       }
     }
     __syncthreads();
-    if (last) {
-      // element e of the tile: its columns (all 16 lanes' sums when F > 16),
-      // each summed over the waves in order
-      const uint32_t ne = min(E, K - t * E);
+    {
+      // output (j, c): element k0 + j of the tile, factor c: its columns in this tile in
+      // order, each summed over the waves in order, after the partial sum carried from the
+      // previous tile when the element began there; written when the element ends here,
+      // else carried into the next tile (slot by tile parity: the slot read here was written
+      // before this tile's first barrier, the slot written is read after the next one)
+      const uint32_t k0 = c0 / F;
+      const uint32_t ne = (c0 + nc - 1u) / F - k0 + 1u;
       if ((uint32_t)tid < ne * 9) {
-        const int e = tid / 9, c = tid % 9;
-        const int lo = F <= 16 ? e * (int)F : 0;
-        const int hi = F <= 16 ? lo + (int)F : 16;
-        double s = 0.0;
-        for (int m = lo; m < hi; ++m) {
+        const uint32_t j = (uint32_t)tid / 9u;
+        const int c = tid % 9;
+        const uint32_t ke = k0 + j;
+        const uint32_t lo = max(ke * F, c0) - c0, hi = min((ke + 1u) * F, c0 + nc) - c0;
+        double s = (j == 0 && ke * F < c0) ? cry[t & 1u][c] : 0.0;
+        for (uint32_t m = lo; m < hi; ++m) {
           double sw = 0.0;
           for (int ww = 0; ww < S::NCH; ++ww) sw += red[ww][m][c];
           s += sw;
         }
-        gG[(int64_t)(t * E + e) * 9 + c] = s;
+        if ((ke + 1u) * F <= c0 + nc)
+          gG[(int64_t)ke * 9 + c] = s;
+        else
+          cry[(t + 1u) & 1u][c] = s;
       }
     }
-    t = t_next;
-    sub = sub_next;
+    ++t;
   }
 }
 

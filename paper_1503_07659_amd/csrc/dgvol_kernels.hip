@@ -255,8 +255,6 @@ struct AdjPlan {
 
 template <int NP>
 static dg_status adj_plan(int64_t K, int32_t F, AdjPlan* pl) {
-  const uint32_t E = F <= 16 ? (uint32_t)(16 / F) : 1u;
-  const uint32_t ntiles = ceil_div((uint64_t)K, E);
   int err = DG_OK;
   if constexpr (NP >= 84) {
     const uint32_t tiles_a = ceil_div((uint64_t)K * (uint64_t)F, 16);
@@ -265,7 +263,7 @@ static dg_status adj_plan(int64_t K, int32_t F, AdjPlan* pl) {
     pl->fn[0] = reinterpret_cast<const void*>(adjcr_gu_kernel<NP>);
     pl->fn[1] = reinterpret_cast<const void*>(adjcr_gG_kernel<NP>);
     pl->units[0] = tiles_a;
-    pl->units[1] = ntiles;
+    pl->units[1] = tiles_a;  // the gG pass: runs of whole elements per workgroup, in 16-column tiles
     for (int i = 0; i < 2; ++i) {
       const int cap = resident_blocks_fn(pl->fn[i], pl->block, -1, &err);
       if (err != DG_OK) return err;
@@ -275,6 +273,9 @@ static dg_status adj_plan(int64_t K, int32_t F, AdjPlan* pl) {
       pl->min_it[i] = pl->units[i] / pl->grid[i];
       pl->max_it[i] = ceil_div(pl->units[i], pl->grid[i]);
     }
+    const uint64_t nw = pl->grid[1];
+    pl->min_it[1] = (uint32_t)ceil_div((uint64_t)(K / nw) * (uint64_t)F, 16);
+    pl->max_it[1] = (uint32_t)ceil_div(ceil_div((uint64_t)K, nw) * (uint64_t)F, 16);
   } else {
     pl->nk = 1;
     pl->block = WAVE * ADJ_WPB;
@@ -297,9 +298,6 @@ static dg_status adj_plan(int64_t K, int32_t F, AdjPlan* pl) {
 template <int NP>
 static dg_status launch_adj_f64(const double* D, const double* G, const double* u, const double* gout,
                                 double* gu, double* gG, int64_t K, int32_t F, hipStream_t stream) {
-  const uint32_t E = F <= 16 ? (uint32_t)(16 / F) : 1u;
-  const uint32_t nsub = F <= 16 ? 1u : ceil_div((uint64_t)F, 16);
-  const uint32_t ntiles = ceil_div((uint64_t)K, E);
   AdjPlan pl;
   const dg_status st = adj_plan<NP>(K, F, &pl);
   if (st != DG_OK) return st;
@@ -309,7 +307,7 @@ static dg_status launch_adj_f64(const double* D, const double* G, const double* 
     hipLaunchKernelGGL(adjcr_gu_kernel<NP>, dim3(pl.grid[0]), dim3(pl.block), 0, stream, D, G, gout, gu,
                        (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP, pl.units[0]);
     hipLaunchKernelGGL(adjcr_gG_kernel<NP>, dim3(pl.grid[1]), dim3(pl.block), 0, stream, D, u, gout, gG, (uint32_t)K,
-                       (uint32_t)F, (int64_t)ncols * NP, E, nsub, ntiles);
+                       (uint32_t)F, (int64_t)ncols * NP);
   } else {
     hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D, G, u,
                        gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP);

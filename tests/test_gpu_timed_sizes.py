@@ -139,15 +139,23 @@ def test_adjoint_three_loop_iterations(N, F):
     check_whole(host(gG), ref_gG, c_gG, what="gG")
 
 
-@pytest.mark.parametrize("N", [1, 4, 5])
-@pytest.mark.parametrize("F", [1, 2, 3, 5, 6, 7, 9, 11, 13, 15, 16, 17, 20, 33, 40])
+def _packed_cases():
+    # orders 1, 4, 5 (staged adjoint: runs per wave) at every F up to 16 and some above;
+    # orders 6, 7 (two-pass adjoint, gG pass: runs per workgroup) at a subset
+    cases = [(N, F) for N in (1, 4, 5) for F in (1, 2, 3, 5, 6, 7, 9, 11, 13, 15, 16, 17, 20, 33, 40)]
+    cases += [(N, F) for N in (6, 7) for F in (1, 3, 7, 16, 17, 40)]
+    return cases
+
+
+@pytest.mark.parametrize("N,F", _packed_cases())
 def test_adjoint_packed_tiles(N, F):
-    """Each wave takes a run of whole elements as full 16-column tiles, so an element
-    can straddle two tiles (F <= 16) or span three or more (F > 16, the middle ones
-    taking and passing on the carry) and carry its partial gG forward.  Every F up to
-    16 (each straddling pattern) and some above, at >= 3 tiles per wave, at an order
-    with guarded loads (1, 4) and one with buffer ranges (5): against the oracle, and
-    the same bits on a second run."""
+    """Each wave (orders 1-5) or workgroup (the gG pass at orders 6, 7) takes a run of
+    whole elements as full 16-column tiles, so an element can straddle two tiles
+    (F <= 16) or span three or more (F > 16, the middle ones taking and passing on the
+    carry) and carry its partial gG forward.  Every F up to 16 (each straddling pattern)
+    and some above at orders with guarded loads (1, 4) and buffer ranges (5), and a
+    subset at orders 6, 7, at >= 3 tiles per worker: against the oracle, and the same
+    bits on a second run."""
     Np = oracle.num_nodes(N)
     K, sh = _k_for_iters(dgvol.OP_ADJOINT, dgvol.FORM_F64, Np, 0, F)
     K += 5  # runs of unequal length
