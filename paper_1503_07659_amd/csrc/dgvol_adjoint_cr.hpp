@@ -27,6 +27,10 @@
 //     next one, so every element's sums finish inside one workgroup.  The
 //     partial sums are added in a fixed order (lane groups, then waves, then
 //     the element's columns in order), so gG is reproducible bit for bit.
+//     The loop takes one barrier per tile: the u stage and the partial sums
+//     are double-buffered, a tile's final sums are formed while the next
+//     tile's products run, and u and gout are requested one tile ahead (two
+//     at Np = 84, where the registers allow it).
 //
 // gout is read twice (once per pass), u once; the matrix work equals the
 // single-pass adjoint's.
@@ -40,6 +44,15 @@
 namespace dgvol {
 
 constexpr int ADJCR_WPB = 8;
+
+// fn(integral_constant<I>), ..., fn(integral_constant<N - 1>), unrolled at compile time
+template <int I, int N, typename Fn>
+__device__ __forceinline__ void adjcr_static_for(Fn&& fn) {
+  if constexpr (I < N) {
+    fn(std::integral_constant<int, I>{});
+    adjcr_static_for<I + 1, N>(fn);
+  }
+}
 
 // ------------------------------------------------------------------ pass A: gu
 
@@ -213,34 +226,45 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
 
 template <int NP>
 struct AdjCrB {
-  static constexpr int NTH = WAVE * ADJCR_WPB;
+  // Tiles per output chunk: 3 (4 whole node triples per lane), but 2 at
+  // Np = 84, whose 16 tiles then give all 8 waves two; with 3-tile chunks two
+  // waves sat idle and one SIMD carried two full chunks.  (One tile for each
+  // of 16 waves, 4 per SIMD, measured 8 % slower: twice the epilogue.)  The
+  // pass only sums gout * (D u) over nodes, so a chunk need not hold whole
+  // triples.
+  static constexpr int WPB = ADJCR_WPB;
+  static constexpr int NTH = WAVE * WPB;
   static constexpr int KS = Shape<NP>::KS64;
   static constexpr int LD = NP + 1;                    // odd row stride of the u stage
   static constexpr int NLD = (16 * NP + NTH - 1) / NTH;
-  // Tiles per output chunk: 3 (4 whole node triples per lane), but 2 at
-  // Np = 84, whose 16 tiles then give all 8 waves two; with 3-tile chunks two
-  // waves sat idle and one SIMD carried two full chunks.  The pass only sums
-  // gout * (D u) over nodes, so a chunk need not hold whole triples.
   static constexpr int TPC = NP == 84 ? 2 : 3;
   static constexpr int NCH = (Shape<NP>::MT + TPC - 1) / TPC;  // chunks (waves with work)
   static constexpr int SPC = 4 * TPC;                         // slots per chunk
   static constexpr int NTRI = SPC % 3 == 0 ? SPC / 3 : (SPC + 4) / 3;  // node triples a chunk touches
-  static_assert(NCH <= ADJCR_WPB, "one wave per output chunk");
+  static_assert(NCH <= WPB, "one wave per output chunk");
   // at Np = 120 the last tile's last KL k-steps' operands wait in LDS
-  static constexpr int KL = NP == 120 ? 8 : 0;
+  static constexpr int KL = NP == 120 ? 12 : 0;
   static constexpr int KR = KS - KL;
+  // tiles of u and gout in flight (register sets); at Np = 120 the registers
+  // hold only one
+  static constexpr int DEPTH = NP == 84 ? 2 : 1;
+  static constexpr bool ALLW = NCH == WPB;  // every wave has a chunk
 };
 
 template <int NP>
-__global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double* __restrict__ D,
+__global__ __launch_bounds__(AdjCrB<NP>::NTH) void adjcr_gG_kernel(const double* __restrict__ D,
                                                                   const double* __restrict__ u,
                                                                   const double* __restrict__ gout,
                                                                   double* __restrict__ gG, uint32_t K, uint32_t F,
                                                                   int64_t plane) {
   using Sh = Shape<NP>;
   using S = AdjCrB<NP>;
-  __shared__ double us[16 * S::LD];
-  __shared__ double red[ADJCR_WPB][16][9];  // per wave and column
+  // double-buffered by tile parity: tile t's products read us[t & 1] and
+  // write red[t & 1] while u of tile t + 1 is staged into the other buffer
+  // and tile t - 1's sums are read from the other red, so one barrier per
+  // tile separates every write from its reads
+  __shared__ double us[2][16 * S::LD];
+  __shared__ double red[2][S::WPB][16][9];  // per tile parity, wave and column
   __shared__ double cry[2][9];  // partial gG of an element continued in the next tile (slot by tile parity)
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -250,7 +274,7 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
   const int ch = mma ? w : 0;
   const int tau0 = S::SPC * ch / 3;  // first node triple of the chunk
   const int r0 = S::SPC * ch % 3;    // its first slot's direction
-  __shared__ double atl[S::KL ? ADJCR_WPB * S::KL * WAVE : 1];  // operand tail, per wave and lane
+  __shared__ double atl[S::KL ? S::WPB * S::KL * WAVE : 1];  // operand tail, per wave and lane
   double areg[S::TPC][S::KS];
 #pragma unroll
   for (int tt = 0; tt < S::TPC; ++tt) {
@@ -270,129 +294,161 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gG_kernel(const double*
   const uint32_t e_hi = (uint32_t)((uint64_t)(blockIdx.x + 1) * K / gridDim.x);
   const uint32_t c_lo = e_lo * F, c_hi = e_hi * F;
   const uint32_t nrun = (c_hi - c_lo + 15u) / 16u;
-  double ur[S::NLD];
   // u and gout move through buffer ranges (32-bit offsets, zero past the
   // range, empty past the last tile), which frees the address registers of
   // the clamped 64-bit form
-  auto load = [&](uint32_t tt) __attribute__((always_inline)) {
+  // tile tt's u and gout wait in register set tt % DEPTH
+  double ur[S::DEPTH][S::NLD];
+  auto load_u = [&](uint32_t tt, auto R) __attribute__((always_inline)) {
+    constexpr int r = decltype(R)::value;
     const bool any = tt < nrun;
     const uint32_t c0 = any ? c_lo + 16u * tt : 0u;
     const uint32_t cnt = any ? min(16u, c_hi - c0) * NP : 0u;
     const __amdgpu_buffer_rsrc_t ru = buffer_range(u + (int64_t)c0 * NP, cnt * 8u);
 #pragma unroll
-    for (int q = 0; q < S::NLD; ++q) ur[q] = buffer_load_f64(ru, (uint32_t)(tid + S::NTH * q) * 8u);
+    for (int q = 0; q < S::NLD; ++q) ur[r][q] = buffer_load_f64(ru, (uint32_t)(tid + S::NTH * q) * 8u);
   };
-  uint32_t t = 0;
-  load(t);
-  while (t < nrun) {
-    const uint32_t c0 = c_lo + 16u * t;
-    const uint32_t nc = min(16u, c_hi - c0);  // valid columns of this tile
+  auto stage = [&](uint32_t b, auto R) __attribute__((always_inline)) {
+    constexpr int r = decltype(R)::value;
 #pragma unroll
     for (int q = 0; q < S::NLD; ++q) {
       const int x = tid + S::NTH * q;
-      if (x < 16 * NP) us[(x / NP) * S::LD + (x % NP)] = ur[q];
+      if (x < 16 * NP) us[b][(x / NP) * S::LD + (x % NP)] = ur[r][q];
     }
-    __syncthreads();
-    load(t + 1);
-    if (mma) {
-      // this lane's gout values, requested before the products (clamped
-      // addresses: unconditional loads; entries outside are zeroed)
-      const uint32_t gbytes = nc * NP * 8u;
-      __amdgpu_buffer_rsrc_t rgo[3];
+  };
+  // this lane's gout values of a tile, requested a tile ahead of their use
+  // (unconditional loads; padding nodes and columns past the tile read the
+  // range's end, which loads zero)
+  double go[S::DEPTH][S::NTRI][3];
+  auto load_go = [&](uint32_t tt, auto R) __attribute__((always_inline)) {
+    constexpr int r = decltype(R)::value;
+    const bool any = tt < nrun;
+    const uint32_t c0 = any ? c_lo + 16u * tt : 0u;
+    const uint32_t gbytes = any ? min(16u, c_hi - c0) * NP * 8u : 0u;
+    __amdgpu_buffer_rsrc_t rgo[3];
 #pragma unroll
-      for (int bb = 0; bb < 3; ++bb) rgo[bb] = buffer_range(gout + bb * plane + (int64_t)c0 * NP, gbytes);
-      double go[S::NTRI][3];
+    for (int bb = 0; bb < 3; ++bb) rgo[bb] = buffer_range(gout + bb * plane + (int64_t)c0 * NP, gbytes);
 #pragma unroll
-      for (int x = 0; x < S::NTRI; ++x) {
-        const int i = 4 * (tau0 + x) + g;
-        // padding nodes read from the range's end, which loads zero
-        const uint32_t off = (tau0 + x < Sh::TRIP && i < NP) ? (uint32_t)(n * NP + i) * 8u : gbytes;
+    for (int x = 0; x < S::NTRI; ++x) {
+      const int i = 4 * (tau0 + x) + g;
+      const uint32_t off = (tau0 + x < Sh::TRIP && i < NP) ? (uint32_t)(n * NP + i) * 8u : gbytes;
 #pragma unroll
-        for (int bb = 0; bb < 3; ++bb) go[x][bb] = buffer_load_f64(rgo[bb], off);
+      for (int bb = 0; bb < 3; ++bb) go[r][x][bb] = buffer_load_f64(rgo[bb], off);
+    }
+  };
+  // products of tile tt and this wave's partial sums into red[tt & 1]
+  auto work = [&](uint32_t tt, auto R) __attribute__((always_inline)) {
+    constexpr int r = decltype(R)::value;
+    const double* ub = us[tt & 1u];
+    f64x4 acc[S::TPC];
+#pragma unroll
+    for (int k = 0; k < S::TPC; ++k) acc[k] = f64x4{0.0, 0.0, 0.0, 0.0};
+    auto bval = [&](int s) __attribute__((always_inline)) {
+      const int j = 4 * s + g;
+      const double v = ub[n * S::LD + min(j, NP - 1)];
+      return j < NP ? v : 0.0;
+    };
+    double bcur = bval(0);
+#pragma unroll
+    for (int s = 0; s < S::KS; ++s) {
+      const double bnxt = s + 1 < S::KS ? bval(s + 1) : 0.0;
+#pragma unroll
+      for (int k = 0; k < S::TPC; ++k) {
+        const double a = (k < S::TPC - 1 || s < S::KR) ? areg[k][s] : atl[(w * S::KL + s - S::KR) * WAVE + lane];
+        acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bcur, acc[k], 0, 0, 0);
       }
-      f64x4 acc[S::TPC];
+      bcur = bnxt;
+    }
+    // P[3a+b] = sum over this lane's nodes of gout_b * (D_a u)
+    double P[9];
 #pragma unroll
-      for (int tt = 0; tt < S::TPC; ++tt) acc[tt] = f64x4{0.0, 0.0, 0.0, 0.0};
-      auto bval = [&](int s) __attribute__((always_inline)) {
-        const int j = 4 * s + g;
-        const double v = us[n * S::LD + min(j, NP - 1)];
-        return j < NP ? v : 0.0;
-      };
-      double bcur = bval(0);
+    for (int c = 0; c < 9; ++c) P[c] = 0.0;
+    // slot l of the chunk: direction (r0 + l) % 3 of its triple (r0 + l) / 3,
+    // with r0 (wave-uniform) made a compile-time constant per branch.  Slots
+    // past the last one need no test: their A rows and their gout (a triple
+    // past the last node) are zero, so they add +0 to P, which leaves it as it is.
+    auto accumulate = [&](auto R0) __attribute__((always_inline)) {
+      constexpr int rr = decltype(R0)::value;
 #pragma unroll
-      for (int s = 0; s < S::KS; ++s) {
-        const double bnxt = s + 1 < S::KS ? bval(s + 1) : 0.0;
-#pragma unroll
-        for (int tt = 0; tt < S::TPC; ++tt) {
-          const double a =
-              (tt < S::TPC - 1 || s < S::KR) ? areg[tt][s] : atl[(w * S::KL + s - S::KR) * WAVE + lane];
-          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bcur, acc[tt], 0, 0, 0);
-        }
-        bcur = bnxt;
+      for (int l = 0; l < S::SPC; ++l) {
+        const int a = (rr + l) % 3, x = (rr + l) / 3;
+        const double R = acc[l >> 2][l & 3];
+        P[3 * a] += go[r][x][0] * R;
+        P[3 * a + 1] += go[r][x][1] * R;
+        P[3 * a + 2] += go[r][x][2] * R;
       }
-      // P[3a+b] = sum over this lane's nodes of gout_b * (D_a u)
-      double P[9];
+    };
+    if (S::SPC % 3 == 0 || r0 == 0)  // 3-tile chunks start on a whole triple
+      accumulate(std::integral_constant<int, 0>{});
+    else if (r0 == 1)
+      accumulate(std::integral_constant<int, 1>{});
+    else
+      accumulate(std::integral_constant<int, 2>{});
 #pragma unroll
-      for (int c = 0; c < 9; ++c) P[c] = 0.0;
-      // slot l of the chunk: direction (r0 + l) % 3 of its triple (r0 + l) / 3,
-      // with r0 (wave-uniform) made a compile-time constant per branch
-      auto accumulate = [&](auto R0) __attribute__((always_inline)) {
-        constexpr int rr = decltype(R0)::value;
+    for (int c = 0; c < 9; ++c) {
+      P[c] += __shfl_xor(P[c], 16);
+      P[c] += __shfl_xor(P[c], 32);
+    }
+    if (g == 0) {
 #pragma unroll
-        for (int l = 0; l < S::SPC; ++l) {
-          const int a = (rr + l) % 3, x = (rr + l) / 3;
-          if (S::SPC * ch + l < Sh::SLOTS) {
-            const double R = acc[l >> 2][l & 3];
-            P[3 * a] += go[x][0] * R;
-            P[3 * a + 1] += go[x][1] * R;
-            P[3 * a + 2] += go[x][2] * R;
-          }
-        }
-      };
-      if (S::SPC % 3 == 0 || r0 == 0)  // 3-tile chunks start on a whole triple
-        accumulate(std::integral_constant<int, 0>{});
-      else if (r0 == 1)
-        accumulate(std::integral_constant<int, 1>{});
+      for (int c = 0; c < 9; ++c) red[tt & 1u][w][n][c] = P[c];
+    }
+  };
+  // output (j, c) of tile tt: element k0 + j, factor c: its columns in the tile in order,
+  // each summed over the waves in order, after the partial sum carried from the previous
+  // tile when the element began there; written when the element ends in this tile, else
+  // carried into the next (slot by tile parity: the slot read was written one barrier
+  // earlier, the slot written is read one barrier later)
+  // The waves take turns (tile tt's outputs start at wave tt % WPB), so that
+  // no SIMD carries every tile's sums.
+  auto reduce = [&](uint32_t tt) __attribute__((always_inline)) {
+    const uint32_t c0 = c_lo + 16u * tt;
+    const uint32_t nc = min(16u, c_hi - c0);
+    const uint32_t k0 = c0 / F;
+    const uint32_t ne = (c0 + nc - 1u) / F - k0 + 1u;
+    const uint32_t o = (uint32_t)(tid - WAVE * (int)(tt % S::WPB)) % (uint32_t)S::NTH;  // output index
+    if (o < ne * 9) {
+      const uint32_t j = o / 9u;
+      const int c = (int)(o % 9u);
+      const uint32_t ke = k0 + j;
+      const uint32_t lo = max(ke * F, c0) - c0, hi = min((ke + 1u) * F, c0 + nc) - c0;
+      double s = (j == 0 && ke * F < c0) ? cry[tt & 1u][c] : 0.0;
+      for (uint32_t m = lo; m < hi; ++m) {
+        double sw = 0.0;
+        for (int ww = 0; ww < S::NCH; ++ww) sw += red[tt & 1u][ww][m][c];
+        s += sw;
+      }
+      if ((ke + 1u) * F <= c0 + nc)
+        gG[(int64_t)ke * 9 + c] = s;
       else
-        accumulate(std::integral_constant<int, 2>{});
-#pragma unroll
-      for (int c = 0; c < 9; ++c) {
-        P[c] += __shfl_xor(P[c], 16);
-        P[c] += __shfl_xor(P[c], 32);
-      }
-      if (g == 0) {
-#pragma unroll
-        for (int c = 0; c < 9; ++c) red[w][n][c] = P[c];
-      }
+        cry[(tt + 1u) & 1u][c] = s;
     }
+  };
+  using I0 = std::integral_constant<int, 0>;
+  load_u(0, I0{});
+  stage(0, I0{});
+  adjcr_static_for<0, S::DEPTH>([&](auto J) {
+    constexpr int j = decltype(J)::value;
+    load_u(j + 1, std::integral_constant<int, (j + 1) % S::DEPTH>{});
+    if (S::ALLW || mma) load_go(j, J);
+  });
+  __syncthreads();
+  // tile t: reduce tile t - 1, products of t, stage u of t + 1; after the barrier request
+  // u of t + 1 + DEPTH and gout of t + DEPTH.  The loop runs whole rounds of DEPTH tiles; a
+  // tile past the run reads zeros and is not reduced.
+  auto step = [&](uint32_t t, auto P) __attribute__((always_inline)) {
+    constexpr int p = decltype(P)::value;
+    using N1 = std::integral_constant<int, (p + 1) % S::DEPTH>;
+    if (t - 1u < nrun) reduce(t - 1u);
+    if (S::ALLW || mma) work(t, P);
+    stage((t + 1u) & 1u, N1{});
     __syncthreads();
-    {
-      // output (j, c): element k0 + j of the tile, factor c: its columns in this tile in
-      // order, each summed over the waves in order, after the partial sum carried from the
-      // previous tile when the element began there; written when the element ends here,
-      // else carried into the next tile (slot by tile parity: the slot read here was written
-      // before this tile's first barrier, the slot written is read after the next one)
-      const uint32_t k0 = c0 / F;
-      const uint32_t ne = (c0 + nc - 1u) / F - k0 + 1u;
-      if ((uint32_t)tid < ne * 9) {
-        const uint32_t j = (uint32_t)tid / 9u;
-        const int c = tid % 9;
-        const uint32_t ke = k0 + j;
-        const uint32_t lo = max(ke * F, c0) - c0, hi = min((ke + 1u) * F, c0 + nc) - c0;
-        double s = (j == 0 && ke * F < c0) ? cry[t & 1u][c] : 0.0;
-        for (uint32_t m = lo; m < hi; ++m) {
-          double sw = 0.0;
-          for (int ww = 0; ww < S::NCH; ++ww) sw += red[ww][m][c];
-          s += sw;
-        }
-        if ((ke + 1u) * F <= c0 + nc)
-          gG[(int64_t)ke * 9 + c] = s;
-        else
-          cry[(t + 1u) & 1u][c] = s;
-      }
-    }
-    ++t;
-  }
+    load_u(t + 1u + S::DEPTH, N1{});
+    if (S::ALLW || mma) load_go(t + S::DEPTH, P);
+  };
+  for (uint32_t t = 0; t < nrun; t += S::DEPTH)
+    adjcr_static_for<0, S::DEPTH>([&](auto P) { step(t + decltype(P)::value, P); });
+  if (nrun > 0 && nrun % S::DEPTH == 0) reduce(nrun - 1);
 }
 
 }  // namespace dgvol

@@ -244,7 +244,7 @@ static double tile_cost_estimate(int form, int Np, uint32_t F) {
 struct AdjPlan {
   int nk;                // kernels launched
   const void* fn[2];
-  uint32_t block;
+  uint32_t block[2];     // threads per workgroup of each kernel
   uint32_t grid[2];
   uint32_t resident[2];
   uint32_t units[2];     // work units of each kernel
@@ -259,13 +259,14 @@ static dg_status adj_plan(int64_t K, int32_t F, AdjPlan* pl) {
   if constexpr (NP >= 84) {
     const uint32_t tiles_a = ceil_div((uint64_t)K * (uint64_t)F, 16);
     pl->nk = 2;
-    pl->block = WAVE * ADJCR_WPB;
+    pl->block[0] = WAVE * ADJCR_WPB;
+    pl->block[1] = AdjCrB<NP>::NTH;
     pl->fn[0] = reinterpret_cast<const void*>(adjcr_gu_kernel<NP>);
     pl->fn[1] = reinterpret_cast<const void*>(adjcr_gG_kernel<NP>);
     pl->units[0] = tiles_a;
     pl->units[1] = tiles_a;  // the gG pass: runs of whole elements per workgroup, in 16-column tiles
     for (int i = 0; i < 2; ++i) {
-      const int cap = resident_blocks_fn(pl->fn[i], pl->block, -1, &err);
+      const int cap = resident_blocks_fn(pl->fn[i], pl->block[i], -1, &err);
       if (err != DG_OK) return err;
       pl->resident[i] = (uint32_t)cap;
       pl->grid[i] = std::min<uint32_t>(pl->units[i], (uint32_t)cap);
@@ -278,9 +279,9 @@ static dg_status adj_plan(int64_t K, int32_t F, AdjPlan* pl) {
     pl->max_it[1] = (uint32_t)ceil_div(ceil_div((uint64_t)K, nw) * (uint64_t)F, 16);
   } else {
     pl->nk = 1;
-    pl->block = WAVE * ADJ_WPB;
+    pl->block[0] = pl->block[1] = WAVE * ADJ_WPB;
     pl->fn[0] = reinterpret_cast<const void*>(adj_f64_staged_kernel<NP, ADJ_WPB>);
-    const int cap = resident_blocks_fn(pl->fn[0], pl->block, -1, &err);
+    const int cap = resident_blocks_fn(pl->fn[0], pl->block[0], -1, &err);
     if (err != DG_OK) return err;
     pl->resident[0] = (uint32_t)cap;
     pl->workers[0] = ADJ_WPB;
@@ -304,12 +305,12 @@ static dg_status launch_adj_f64(const double* D, const double* G, const double* 
   if constexpr (NP >= 84) {
     // two chunk-register passes: gu, then gG
     const uint64_t ncols = (uint64_t)K * (uint64_t)F;
-    hipLaunchKernelGGL(adjcr_gu_kernel<NP>, dim3(pl.grid[0]), dim3(pl.block), 0, stream, D, G, gout, gu,
+    hipLaunchKernelGGL(adjcr_gu_kernel<NP>, dim3(pl.grid[0]), dim3(pl.block[0]), 0, stream, D, G, gout, gu,
                        (uint32_t)ncols, (uint32_t)F, (int64_t)ncols * NP, pl.units[0]);
-    hipLaunchKernelGGL(adjcr_gG_kernel<NP>, dim3(pl.grid[1]), dim3(pl.block), 0, stream, D, u, gout, gG, (uint32_t)K,
+    hipLaunchKernelGGL(adjcr_gG_kernel<NP>, dim3(pl.grid[1]), dim3(pl.block[1]), 0, stream, D, u, gout, gG, (uint32_t)K,
                        (uint32_t)F, (int64_t)ncols * NP);
   } else {
-    hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB>), dim3(pl.grid[0]), dim3(pl.block), 0, stream, D, G, u,
+    hipLaunchKernelGGL((adj_f64_staged_kernel<NP, ADJ_WPB>), dim3(pl.grid[0]), dim3(pl.block[0]), 0, stream, D, G, u,
                        gout, gu, gG, (uint32_t)K, (uint32_t)F, (int64_t)K * F * NP);
   }
   return hipGetLastError() == hipSuccess ? DG_OK : DG_ELAUNCH;
@@ -685,7 +686,7 @@ dg_status dg_launch_shape_query(int32_t op, int32_t form, int32_t Np, int32_t va
     }
     if (st != DG_OK) return st;
     sh.grid = pl.grid[0];
-    sh.block = pl.block;
+    sh.block = pl.block[0];
     sh.lds_bytes = 0;
     sh.resident = pl.resident[0];
     sh.units = pl.units[0];
