@@ -218,8 +218,10 @@ typedef struct dg_group {
  * the batch makes one launch per class, in class order, on `stream`.
  * `groups` is a host array of `ngroups` descriptors; it is read during the
  * call only.  Within a launch, the resident workgroups are split between
- * groups by cost x tiles, so that the largest cost per workgroup is as small
- * as possible (every group gets at least one; Jefferson apportionment).  The
+ * groups so that the largest load of a workgroup (its loop steps times the
+ * group's cost per step) is as small as possible: every group gets one, and
+ * each further workgroup goes to the group whose workgroups carry the largest
+ * load.  The
  * split is static: the launch needs no device-side state and can be captured
  * in a HIP graph.  Each group's out is exactly what dg_volume_variant would
  * write for that group alone with the same variant.

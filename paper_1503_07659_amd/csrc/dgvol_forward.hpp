@@ -25,6 +25,8 @@
 // LDS from one dynamic buffer, so the same code serves every launch shape.
 #pragma once
 
+#include <type_traits>
+
 #include "dgvol_device.hpp"
 
 namespace dgvol {
@@ -491,10 +493,25 @@ constexpr int chunk_us_bytes() {
   return WORD == 8 ? TPW * 16 * chunk_ld<NP, WORD>() * WORD : 2 * TPW * 16 * chunk_ldb<NP>() * 2;
 }
 
+// FP64 at Np = 84: 16 row tiles make 6 chunks of at most 3 tiles for 8
+// waves, two SIMDs of four would carry 6 tiles and two 3.  There the two
+// spare waves take the last k-steps of two chunks and write their partial
+// outputs into a second output tile, which the stores add.
+template <int NP, int WORD>
+constexpr bool chunk_sum2() { return WORD == 8 && NP == 84; }
+
+// Byte offset of the second output tile (after the u stage, the output tile
+// and the geometric factors).
+template <int NP, int WORD, int TPW>
+constexpr int chunk_out2_offset() {
+  return align16(chunk_us_bytes<NP, WORD, TPW>()) + align16(3 * TPW * 16 * chunk_old<NP, WORD>() * WORD) +
+         align16(TPW * 16 * 9 * WORD);
+}
+
 template <int NP, int WORD, int TPW>
 constexpr int chunk_lds() {
-  return align16(chunk_us_bytes<NP, WORD, TPW>()) + align16(3 * TPW * 16 * chunk_old<NP, WORD>() * WORD) +
-         TPW * 16 * 9 * WORD;
+  return chunk_out2_offset<NP, WORD, TPW>() +
+         (chunk_sum2<NP, WORD>() ? 3 * TPW * 16 * chunk_old<NP, WORD>() * WORD : 0);
 }
 
 template <int NP, int WPB, int TPW>
@@ -527,6 +544,8 @@ __device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t 
   char* us = lds;  // laid out by put_u (the body's staging of one u word)
   T* ostg = reinterpret_cast<T*>(lds + align16(chunk_us_bytes<NP, WORD, TPW>()));
   T* gs = reinterpret_cast<T*>(lds + align16(chunk_us_bytes<NP, WORD, TPW>()) + align16(3 * OSUP * WORD));
+  constexpr bool SUM2 = chunk_sum2<NP, WORD>();
+  const T* ostg2 = reinterpret_cast<const T*>(lds + chunk_out2_offset<NP, WORD, TPW>());
   const int tid = threadIdx.x;
   const uint32_t nsup = (p.ntiles + TPW - 1) / TPW;
   T ur[NLD][VEC];
@@ -589,13 +608,15 @@ __device__ __forceinline__ void chunkreg_loop_vec(const FwdArgs<T>& p, uint32_t 
       for (int q = 0; q < NLD; ++q) {
         const int x0 = (tid + NT * q) * VEC;
         const int xc = min(x0, SUP - VEC);
-        const T* src = ostg + bb * OSUP + (xc / NP) * OLD + (xc % NP);
+        const int so = bb * OSUP + (xc / NP) * OLD + (xc % NP);
+        const T* src = ostg + so;
+        const T* src2 = ostg2 + so;  // read only with SUM2
         if constexpr (VEC == 1) {
-          buffer_store_stream_word(ro, (uint32_t)x0 * WORD, src[0]);
+          buffer_store_stream_word(ro, (uint32_t)x0 * WORD, SUM2 ? src[0] + src2[0] : src[0]);
         } else {
           WordVec<T, VEC> v;
 #pragma unroll
-          for (int e = 0; e < VEC; ++e) v.v[e] = src[e];
+          for (int e = 0; e < VEC; ++e) v.v[e] = SUM2 ? src[e] + src2[e] : src[e];
           buffer_store_stream_vec<T, VEC>(ro, (uint32_t)x0 * WORD, v);
         }
       }
@@ -633,8 +654,19 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
   const int lane = threadIdx.x & 63;
   const int n = lane & 15, g = lane >> 4;
   const int w = threadIdx.x >> 6;
-  const bool mma = w < Sh::NCHUNK;
-  const int ch = mma ? w : 0;
+  // Wave roles.  Without the split, wave w < NCHUNK runs chunk w whole.  With
+  // it (Np = 84, chunks 0-4 of 3 tiles and chunk 5 of 1): waves 0 and 4 run
+  // the first KH k-steps of chunks 0 and 4, waves 6 and 7 the rest of them
+  // into the second output tile, and wave 5 its one tile, so that every SIMD
+  // (waves s and s + 4) carries 84 tile k-steps where two carried 126.
+  constexpr bool SPLIT = chunk_sum2<NP, 8>();
+  static_assert(!SPLIT || (WPB == 8 && Sh::NCHUNK == 6 && Sh::MT == 16), "the split assumes 6 chunks on 8 waves");
+  constexpr int KH = SPLIT ? 14 : KS;
+  const bool helper = SPLIT && w >= 6;
+  const bool mma = w < Sh::NCHUNK || helper;
+  const int ch = helper ? (w == 6 ? 0 : 4) : (mma ? w : 0);
+  // 0: whole chunk; 1: first KH k-steps; 2: k-steps from KH on; 3: one tile (the last chunk)
+  const int role = !SPLIT ? 0 : helper ? 2 : (w == 0 || w == 4) ? 1 : w == 5 ? 3 : 0;
   // this wave's A operands, for the whole launch
   double areg[3][KS];
 #pragma unroll
@@ -643,10 +675,17 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
 #pragma unroll
     for (int s = 0; s < KS; ++s) areg[tt][s] = (mma && T < Sh::MT) ? afrag_f64<NP>(p.D, T, s, lane) : 0.0;
   }
+  // the second output tile holds -0.0 wherever no helper writes (x + -0.0 == x)
+  if constexpr (SPLIT) {
+    double* o2 = reinterpret_cast<double*>(lds + chunk_out2_offset<NP, 8, TPW>());
+    for (int x = threadIdx.x; x < 3 * OSUP; x += WAVE * WPB) o2[x] = -0.0;
+  }
+  double* ostg2 = reinterpret_cast<double*>(lds + chunk_out2_offset<NP, 8, TPW>());
   auto put_u = [](char* us, int c, int i, double v) { reinterpret_cast<double*>(us)[c * LD + i] = v; };
   auto chunk = [&](const char* usb, double* ostg, const double* gs, uint32_t col0, uint32_t k_lo) {
     if (!mma) return;
     const double* us = reinterpret_cast<const double*>(usb);
+    double* dst = helper ? ostg2 : ostg;
 #pragma unroll
     for (int tp = 0; tp < TPW; ++tp) {
       const int cl = tp * 16 + n;  // column within the super-tile
@@ -658,15 +697,32 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
         const double v = us[cl * LD + min(j, NP - 1)];
         return j < NP ? v : 0.0;
       };
-      double bcur = bval(0);
+      // tiles [0, NT) of the chunk over k-steps [S0, S1)
+      auto run = [&](auto NTc, auto S0c, auto S1c) __attribute__((always_inline)) {
+        constexpr int NTT = decltype(NTc)::value, S0 = decltype(S0c)::value, S1 = decltype(S1c)::value;
+        double bcur = bval(S0);
 #pragma unroll
-      for (int s = 0; s < KS; ++s) {
-        const double bnxt = s + 1 < KS ? bval(s + 1) : 0.0;
+        for (int s = S0; s < S1; ++s) {
+          const double bnxt = s + 1 < S1 ? bval(s + 1) : 0.0;
 #pragma unroll
-        for (int tt = 0; tt < 3; ++tt)  // a missing third tile of the last chunk has zero operands
-          acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[tt][s], bcur, acc[tt], 0, 0, 0);
-        bcur = bnxt;
-      }
+          for (int tt = 0; tt < NTT; ++tt)  // a missing third tile of the last chunk has zero operands
+            acc[tt] = __builtin_amdgcn_mfma_f64_16x16x4f64(areg[tt][s], bcur, acc[tt], 0, 0, 0);
+          bcur = bnxt;
+        }
+      };
+      using C0 = std::integral_constant<int, 0>;
+      using C1 = std::integral_constant<int, 1>;
+      using C3 = std::integral_constant<int, 3>;
+      using CKH = std::integral_constant<int, KH>;
+      using CKS = std::integral_constant<int, KS>;
+      if (!SPLIT || role == 0)
+        run(C3{}, C0{}, CKS{});
+      else if (role == 1)
+        run(C3{}, C0{}, CKH{});
+      else if (role == 2)
+        run(C3{}, CKH{}, CKS{});
+      else
+        run(C1{}, C0{}, CKS{});
       const uint32_t col = col0 + cl;
       const int e = (int)(min(col, p.ncols - 1) / p.F - k_lo);
 #pragma unroll
@@ -677,9 +733,9 @@ __device__ __forceinline__ void fwd_f64_chunkreg_body(const FwdArgs<double>& p, 
           const int l0 = 3 * x;
 #pragma unroll
           for (int bb = 0; bb < 3; ++bb)
-            ostg[bb * OSUP + cl * OLD + i] = gs[e * 9 + bb] * acc[l0 >> 2][l0 & 3] +
-                                           gs[e * 9 + 3 + bb] * acc[(l0 + 1) >> 2][(l0 + 1) & 3] +
-                                           gs[e * 9 + 6 + bb] * acc[(l0 + 2) >> 2][(l0 + 2) & 3];
+            dst[bb * OSUP + cl * OLD + i] = gs[e * 9 + bb] * acc[l0 >> 2][l0 & 3] +
+                                          gs[e * 9 + 3 + bb] * acc[(l0 + 1) >> 2][(l0 + 1) & 3] +
+                                          gs[e * 9 + 6 + bb] * acc[(l0 + 2) >> 2][(l0 + 2) & 3];
         }
       }
     }

@@ -232,7 +232,7 @@ static double tile_cost_estimate(int form, int Np, uint32_t F) {
     case 20: eff = form == DG_FORM_F64 ? 0.67 : 0.60; break;
     case 35: eff = form == DG_FORM_F64 ? 0.60 : 0.55; break;
     case 56: eff = form == DG_FORM_F64 ? 0.58 : 0.76; break;
-    case 84: eff = form == DG_FORM_F64 ? 0.43 : 0.70; break;
+    case 84: eff = form == DG_FORM_F64 ? 0.54 : 0.70; break;
     default: eff = form == DG_FORM_F64 ? 0.60 : 0.55; break;  // Np = 120
   }
   return std::max(bytes / bw, flops / peak) / eff;
@@ -571,9 +571,9 @@ dg_status dg_volume_batched(const dg_group* groups, int32_t ngroups, int32_t F, 
   for (int cls = 0; cls < NUM_LCLASSES; ++cls) {
     BatchArgs a{};
     a.F = (uint32_t)F;
-    double cost[DG_MAX_GROUPS];
+    double step_cost[DG_MAX_GROUPS];  // estimated cost of one loop step of one workgroup
+    uint32_t steps[DG_MAX_GROUPS];    // loop steps of the group (units over units per step)
     uint32_t max_blocks[DG_MAX_GROUPS];
-    double total_cost = 0.0;
     int lds = 0;
     int ng = 0;
     for (int i = 0; i < ngroups; ++i) {
@@ -591,9 +591,9 @@ dg_status dg_volume_batched(const dg_group* groups, int32_t ngroups, int32_t F, 
       gd.u = gr.u;
       gd.out = gr.out;
       const double per_tile = gr.cost > 0.0 ? gr.cost : tile_cost_estimate(form, gr.Np, (uint32_t)F);
-      cost[ng] = per_tile * gd.ntiles;
-      max_blocks[ng] = ceil_div(gd.ntiles, units_per_step(desc[i]));
-      total_cost += cost[ng];
+      step_cost[ng] = per_tile * units_per_step(desc[i]);
+      steps[ng] = ceil_div(gd.ntiles, units_per_step(desc[i]));
+      max_blocks[ng] = steps[ng];
       lds = std::max(lds, desc[i].lds);
       ++ng;
     }
@@ -604,23 +604,26 @@ dg_status dg_volume_batched(const dg_group* groups, int32_t ngroups, int32_t F, 
     const int block = WAVE * class_waves(cls);
     const int cap = resident_blocks_fn(fn, block, lds, &err);
     if (err != DG_OK) return err;
-    // Split the resident workgroups so that the largest cost per workgroup is as
-    // small as possible (Jefferson / D'Hondt apportionment): every group gets the
-    // whole part of its proportional share, at least one and at most what it can
-    // use, then each workgroup left goes to the group with the largest cost per
-    // workgroup.  Plain rounding of the shares can leave a small group one
-    // workgroup short, and that group then finishes last.
+    // Split the resident workgroups so that the largest load of a workgroup is as
+    // small as possible: every group starts with one workgroup, and each further
+    // one goes to the group whose workgroups carry the largest load, at most as
+    // many as the group has loop steps.  A workgroup's load is its loop steps
+    // (the group's steps over its workgroups, rounded up) times the cost of a
+    // step.  Giving each group the whole part of its proportional share first
+    // had used up the workgroups on the floors and the groups bumped to one,
+    // and left a small group (order 6 of the mixed batch) one workgroup short:
+    // it then finished last.
     uint32_t nb[DG_MAX_GROUPS];
     uint32_t used = 0;
     for (int i = 0; i < ng; ++i) {
-      const uint32_t share = (uint32_t)((double)cap * cost[i] / total_cost);
-      nb[i] = std::max<uint32_t>(1u, std::min(share, max_blocks[i]));
-      used += nb[i];
+      nb[i] = 1;
+      ++used;
     }
+    auto load = [&](int i) { return step_cost[i] * (double)ceil_div(steps[i], nb[i]); };
     while (used < (uint32_t)cap) {
       int pick = -1;
       for (int i = 0; i < ng; ++i)
-        if (nb[i] < max_blocks[i] && (pick < 0 || cost[i] * nb[pick] > cost[pick] * nb[i])) pick = i;
+        if (nb[i] < max_blocks[i] && (pick < 0 || load(i) > load(pick))) pick = i;
       if (pick < 0) break;
       ++nb[pick];
       ++used;
