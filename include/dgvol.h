@@ -75,13 +75,17 @@ typedef int32_t dg_status;
 
 #define DG_MAX_GROUPS 16
 
-/* Version of this interface (DGVOL_ABI_VERSION of the built library). */
+/* Version of this interface (DGVOL_ABI_VERSION of the built library).
+ * Source: this library's interface. */
 int32_t dg_abi_version(void);
 
-/* Static description of a status code; never NULL. */
+/* Static description of a status code; never NULL.  Source: this library's
+ * interface. */
 const char *dg_strerror(dg_status status);
 
-/* 1 if Np is a supported node count, else 0. */
+/* 1 if Np is a supported node count, else 0.  Source: the node count of a
+ * degree-N nodal basis on the tetrahedron, Np = (N+1)(N+2)(N+3)/6; the range
+ * N = 1..7 (Np = 4, 10, 20, 35, 56, 84, 120) is this library's. */
 int32_t dg_supported_np(int32_t Np);
 
 /*
@@ -144,7 +148,8 @@ dg_status dg_volume_grad_d(const double *G, const double *u, const double *gout,
                            int64_t K, int32_t Np, int32_t F, void *stream);
 
 /* Scratch bytes dg_volume_grad_d needs for (K, Np, F), written to *bytes (may
- * be 0).  Pure host computation.  Errors: DG_EINVAL, DG_EUNSUPPORTED. */
+ * be 0).  Pure host computation.  Source: this library's (the partition of
+ * dg_volume_grad_d).  Errors: DG_EINVAL, DG_EUNSUPPORTED. */
 dg_status dg_volume_grad_d_workspace(int64_t K, int32_t Np, int32_t F, uint64_t *bytes);
 
 /*
@@ -255,10 +260,13 @@ typedef struct dg_variant_info {
   int32_t lds_bytes;     /* dynamic LDS per workgroup */
 } dg_variant_info;
 
-/* Number of variants for (form, Np); 0 if either is unsupported.  Pure host. */
+/* Number of variants for (form, Np); 0 if either is unsupported.  Pure host.
+ * Source: the launch shapes are this library's; choosing among them per order
+ * is the paper's autotuning use case (Introduction). */
 int32_t dg_variant_count(int32_t form, int32_t Np);
 
 /* Describe variant `variant` of (form, Np) into *info (host memory).  Pure host.
+ * Source: as dg_variant_count.
  * Errors: DG_EINVAL (info NULL), DG_EUNSUPPORTED (form, Np or variant out of range). */
 dg_status dg_variant_query(int32_t form, int32_t Np, int32_t variant, dg_variant_info *info);
 
@@ -268,7 +276,9 @@ dg_status dg_variant_query(int32_t form, int32_t Np, int32_t variant, dg_variant
  * `variant` DG_VARIANT_AUTO or an index < dg_variant_count(form, Np).  The
  * result meets the same bound as the form's default entry point (FP64: the
  * same reference values up to summation order; split-BF16: the same stated
- * bound).  Errors as for dg_volume, plus DG_EUNSUPPORTED for the variant.
+ * bound).  Source: the operation of dg_volume (FP64) or dg_volume_f32s; the
+ * variants are this library's launch shapes (see dg_variant_count).
+ * Errors as for dg_volume, plus DG_EUNSUPPORTED for the variant.
  */
 dg_status dg_volume_variant(int32_t form, int32_t variant, const void *D, const void *G, const void *u,
                             void *out, int64_t K, int32_t Np, int32_t F, void *stream);
@@ -281,7 +291,8 @@ dg_status dg_volume_variant(int32_t form, int32_t variant, const void *D, const 
  * elements, taken as 16-column tiles (at Np = 84, 120 its second pass gives
  * such a run to each workgroup).  min_iters is the loop iterations of the
  * least-loaded wave (or workgroup, for the workgroup-wide loops), taken over
- * every kernel the operation launches.
+ * every kernel the operation launches.  Source: this library's (a description
+ * of its own launches, for tests and tuning).
  */
 typedef struct dg_launch_shape {
   uint32_t grid;            /* workgroups launched (first kernel of the operation) */
@@ -311,7 +322,8 @@ dg_status dg_launch_shape_query(int32_t op, int32_t form, int32_t Np, int32_t va
  * With copies = 1 it is a plain copy of known size, used to scale hardware
  * byte counters; with copies = 3 it moves bytes in the same 1 : 3 read : write
  * mix as dg_volume with no other work, which measures the practical streaming
- * ceiling for that mix.  When src and dst are 16-byte aligned and n is even,
+ * ceiling for that mix.  Source: this library's (a measurement of the chip,
+ * not DG work).  When src and dst are 16-byte aligned and n is even,
  * every thread moves several independent 16-byte pairs in a one-pass grid;
  * otherwise single words in a grid-stride loop.  Errors: DG_EINVAL (n < 0,
  * copies outside 1..3, null or misaligned pointer with n > 0), DG_EDEVICE,
@@ -331,7 +343,8 @@ dg_status dg_stream_calibrate(const double *src, double *dst, int64_t n, int32_t
  * wave taking m tiles (m = 1: the grid covers the array once);
  * tiles_per_wave = 0: one 8-wave workgroup per CU looping over all tiles, the
  * launch shape of the forward kernel.  Timed by the caller, it separates the
- * cost of the launch shape from the cost of the arithmetic.
+ * cost of the launch shape from the cost of the arithmetic.  Source: this
+ * library's (a measurement of the chip, not DG work).
  * Errors: DG_EINVAL (ntiles < 0 or too large, tiles_per_wave < 0, null or
  * misaligned pointer with ntiles > 0), DG_EDEVICE, DG_ELAUNCH.
  */
@@ -345,6 +358,7 @@ dg_status dg_stream_calibrate_tiles(const double *src, double *dst, int64_t ntil
  * from registers, i.e. DG_MFMA_CAL_BLOCKS * 4 * iters * 4 * 2048 flops in all,
  * and writes one double per thread to sink[0 .. DG_MFMA_CAL_BLOCKS * 256).
  * Timed by the caller, it gives the attainable FP64 matrix rate of the device.
+ * Source: this library's (a measurement of the chip, not DG work).
  * Errors: DG_EINVAL (null or misaligned sink, iters < 1), DG_ELAUNCH.
  */
 #define DG_MFMA_CAL_BLOCKS 2048
