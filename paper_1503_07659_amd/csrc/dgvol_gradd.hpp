@@ -73,6 +73,16 @@ struct GdShape {
   static_assert(2 * LDS_DOUBLES * 8 <= 160 * 1024, "two workgroups per CU");
   static_assert(GD_UNIT % CH == 0 && CH % 4 == 0, "staging step");
   static_assert((CH / 4) % KSPLIT == 0, "k steps split evenly");
+  // directions whose W rows one workgroup holds (its geometric factors in registers)
+  static constexpr int NDIR = NSPLIT > 1 ? 2 : 3;
+  static constexpr bool dirs_fit() {
+    for (int s = 0; s < NSPLIT; ++s) {
+      const int r0 = s * RTS * 16, r1 = (s + 1) * RTS * 16 < 3 * NP ? (s + 1) * RTS * 16 : 3 * NP;
+      if (r0 < r1 && (r1 - 1) / NP - r0 / NP + 1 > NDIR) return false;
+    }
+    return true;
+  }
+  static_assert(dirs_fit(), "a workgroup's rows span at most NDIR directions");
 };
 
 struct GdArgs {
@@ -125,7 +135,10 @@ void gd_partial_kernel(GdArgs p) {
   // this thread's column within a step and its first row
   const int cc = tid / S::TPC;
   const int rr = tid % S::TPC;
-  double ru[S::NXU], rg0[S::NXU], rg1[S::NXU], rg2[S::NXU], rG[9];
+  // the workgroup's rows start in direction a_lo and span at most NDIR directions;
+  // rG holds the geometric factors of those (rows 3 a .. 3 a + 2 of the element's 9)
+  const int a_lo = S::NSPLIT > 1 ? r0 / NP : 0;
+  double ru[S::NXU], rg0[S::NXU], rg1[S::NXU], rg2[S::NXU], rG[3 * S::NDIR];
   auto load = [&](uint32_t st) __attribute__((always_inline)) {
     const uint32_t col = st * CH + cc;
     const bool v = col < p.ncols;
@@ -141,7 +154,9 @@ void gd_partial_kernel(GdArgs p) {
     }
     const int64_t gb = (int64_t)(v ? col / p.F : 0u) * 9;
 #pragma unroll
-    for (int m = 0; m < 9; ++m) rG[m] = v ? p.G[gb + m] : 0.0;
+    for (int d = 0; d < S::NDIR; ++d)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) rG[3 * d + b] = v ? p.G[gb + 3 * min(a_lo + d, 2) + b] : 0.0;
   };
 
   // write the registers' step into staging buffer b
@@ -154,10 +169,10 @@ void gd_partial_kernel(GdArgs p) {
       if (i < NP) {
         ul[cc * S::LDU + i] = ru[q];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          const int r = a * NP + i;
+        for (int d = 0; d < S::NDIR; ++d) {
+          const int r = (a_lo + d) * NP + i;
           if (r >= r0 && r < r1)
-            wl[cc * S::LDW + (r - r0)] = rG[3 * a] * rg0[q] + rG[3 * a + 1] * rg1[q] + rG[3 * a + 2] * rg2[q];
+            wl[cc * S::LDW + (r - r0)] = rG[3 * d] * rg0[q] + rG[3 * d + 1] * rg1[q] + rG[3 * d + 2] * rg2[q];
         }
       }
     }
