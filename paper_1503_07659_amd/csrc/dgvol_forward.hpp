@@ -493,10 +493,10 @@ constexpr int chunk_us_bytes() {
   return WORD == 8 ? TPW * 16 * chunk_ld<NP, WORD>() * WORD : 2 * TPW * 16 * chunk_ldb<NP>() * 2;
 }
 
-// FP64 at Np = 84: 16 row tiles make 6 chunks of at most 3 tiles for 8
-// waves, two SIMDs of four would carry 6 tiles and two 3.  There the two
-// spare waves take the last k-steps of two chunks and write their partial
-// outputs into a second output tile, which the stores add.
+// FP64 at Np = 84 the 16 row tiles make 6 chunks (five of 3 tiles, one of 1)
+// for 8 waves; as plain chunks two of the four SIMDs would carry 6 tiles and
+// two 3.  There the two spare waves take the last k-steps of two chunks and
+// write their partial outputs into a second output tile, which the stores add.
 template <int NP, int WORD>
 constexpr bool chunk_sum2() { return WORD == 8 && NP == 84; }
 
