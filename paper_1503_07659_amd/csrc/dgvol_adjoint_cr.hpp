@@ -18,7 +18,7 @@
 //     runs its k-steps, and gu leaves through an LDS tile as contiguous runs.
 //   pass B (gG):  gG[k][3a+b] = sum_f sum_i gout_b[c][i] (D_a u)[c][i].
 //     Wave w < NCH keeps the A operands of output chunk w (3 tiles, as the
-//     forward chunk-register body, or 2 at Np = 84 so that all 8 waves work),
+//     forward chunk-register body; at Np = 84, 4 tiles in 4-wave workgroups),
 //     recomputes D u for the chunk's slots from u staged in LDS, and reduces
 //     it with gout at its lanes' nodes (at most 4 node triples).  Each
 //     workgroup owns a run of whole elements and takes its columns as full
@@ -29,8 +29,7 @@
 //     the element's columns in order), so gG is reproducible bit for bit.
 //     The loop takes one barrier per tile: the u stage and the partial sums
 //     are double-buffered, a tile's final sums are formed while the next
-//     tile's products run, and u and gout are requested one tile ahead (two
-//     at Np = 84, where the registers allow it).
+//     tile's products run, and u and gout are requested one tile ahead.
 //
 // gout is read twice (once per pass), u once; the matrix work equals the
 // single-pass adjoint's.
@@ -226,33 +225,46 @@ __global__ __launch_bounds__(WAVE* ADJCR_WPB) void adjcr_gu_kernel(const double*
 
 template <int NP>
 struct AdjCrB {
-  // Tiles per output chunk: 3 (4 whole node triples per lane), but 2 at
-  // Np = 84, whose 16 tiles then give all 8 waves two; with 3-tile chunks two
-  // waves sat idle and one SIMD carried two full chunks.  (One tile for each
-  // of 16 waves, 4 per SIMD, measured 8 % slower: twice the epilogue.)  The
-  // pass only sums gout * (D u) over nodes, so a chunk need not hold whole
-  // triples.
-  static constexpr int WPB = ADJCR_WPB;
+  // Waves per workgroup and tiles per output chunk.  Np = 120: 8 waves of
+  // 3-tile chunks (4 whole node triples per lane).  Np = 84: 4 waves of
+  // 4-tile chunks, two workgroups per CU.  The two workgroups keep their own
+  // barriers, so one's epilogue and barrier wait run beside the other's
+  // products, where one 8-wave workgroup (2-tile chunks) left each SIMD's
+  // matrix unit idle while both its waves finished a tile; and each tile's
+  // shuffles and partial sums are shared by 4 waves, not 8.  (One tile for
+  // each of 16 waves measured 8 % slower than 8 waves: twice the epilogue.)
+  // The pass only sums gout * (D u) over nodes, so a chunk need not hold
+  // whole triples.
+  static constexpr int WPB = NP == 84 ? 4 : ADJCR_WPB;
   static constexpr int NTH = WAVE * WPB;
   static constexpr int KS = Shape<NP>::KS64;
   static constexpr int LD = NP + 1;                    // odd row stride of the u stage
   static constexpr int NLD = (16 * NP + NTH - 1) / NTH;
-  static constexpr int TPC = NP == 84 ? 2 : 3;
+  static constexpr int TPC = NP == 84 ? 4 : 3;
   static constexpr int NCH = (Shape<NP>::MT + TPC - 1) / TPC;  // chunks (waves with work)
   static constexpr int SPC = 4 * TPC;                         // slots per chunk
   static constexpr int NTRI = SPC % 3 == 0 ? SPC / 3 : (SPC + 4) / 3;  // node triples a chunk touches
   static_assert(NCH <= WPB, "one wave per output chunk");
   // at Np = 120 the last tile's last KL k-steps' operands wait in LDS
-  static constexpr int KL = NP == 120 ? 12 : 0;
+  // A operands kept in LDS instead of registers: the last KL k-steps of the
+  // chunk's last tile and the last KL2 of the one before it (at Np = 84 the
+  // whole last tile and 3 more, which fills two workgroups' 160 KiB)
+  static constexpr int KL = NP == 120 ? 12 : (NP == 84 ? KS : 0);
   static constexpr int KR = KS - KL;
-  // tiles of u and gout in flight (register sets); at Np = 120 the registers
-  // hold only one
-  static constexpr int DEPTH = NP == 84 ? 2 : 1;
+  static constexpr int KL2 = NP == 84 ? 3 : 0;
+  static constexpr int KR2 = KS - KL2;
+  static constexpr int NAT = KL + KL2;  // operands per lane in LDS
+  static_assert(TPC >= 2 || KL2 == 0, "a second tile to take the tail from");
+  // tiles of u and gout in flight (register sets): the registers hold one
+  static constexpr int DEPTH = 1;
+  // waves per SIMD the register budget must allow (two workgroups per CU at Np = 84)
+  static constexpr int MINW = 2;
   static constexpr bool ALLW = NCH == WPB;  // every wave has a chunk
 };
 
 template <int NP>
-__global__ __launch_bounds__(AdjCrB<NP>::NTH) void adjcr_gG_kernel(const double* __restrict__ D,
+__global__ __launch_bounds__(AdjCrB<NP>::NTH)
+__attribute__((amdgpu_waves_per_eu(AdjCrB<NP>::MINW, 8))) void adjcr_gG_kernel(const double* __restrict__ D,
                                                                   const double* __restrict__ u,
                                                                   const double* __restrict__ gout,
                                                                   double* __restrict__ gG, uint32_t K, uint32_t F,
@@ -274,7 +286,11 @@ __global__ __launch_bounds__(AdjCrB<NP>::NTH) void adjcr_gG_kernel(const double*
   const int ch = mma ? w : 0;
   const int tau0 = S::SPC * ch / 3;  // first node triple of the chunk
   const int r0 = S::SPC * ch % 3;    // its first slot's direction
-  __shared__ double atl[S::KL ? S::WPB * S::KL * WAVE : 1];  // operand tail, per wave and lane
+  __shared__ double atl[S::NAT ? S::WPB * S::NAT * WAVE : 1];  // operand tails, per wave and lane
+  // where operand (tile tt of the chunk, k-step s) lives: -1 in registers, else its LDS slot
+  auto tail_slot = [](int tt, int s) constexpr {
+    return (tt == S::TPC - 1 && s >= S::KR) ? s - S::KR : (tt == S::TPC - 2 && s >= S::KR2) ? S::KL + s - S::KR2 : -1;
+  };
   double areg[S::TPC][S::KS];
 #pragma unroll
   for (int tt = 0; tt < S::TPC; ++tt) {
@@ -282,10 +298,10 @@ __global__ __launch_bounds__(AdjCrB<NP>::NTH) void adjcr_gG_kernel(const double*
 #pragma unroll
     for (int s = 0; s < S::KS; ++s) {
       const double a = (mma && T < Sh::MT) ? afrag_f64<NP>(D, T, s, lane) : 0.0;
-      if (tt < S::TPC - 1 || s < S::KR)
+      if (tail_slot(tt, s) < 0)
         areg[tt][s] = a;
       else
-        atl[(w * S::KL + s - S::KR) * WAVE + lane] = a;  // read back by this lane only
+        atl[(w * S::NAT + tail_slot(tt, s)) * WAVE + lane] = a;  // read back by this lane only
     }
   }
   // this workgroup's run of elements [e_lo, e_hi), columns [c_lo, c_hi),
@@ -354,7 +370,7 @@ __global__ __launch_bounds__(AdjCrB<NP>::NTH) void adjcr_gG_kernel(const double*
       const double bnxt = s + 1 < S::KS ? bval(s + 1) : 0.0;
 #pragma unroll
       for (int k = 0; k < S::TPC; ++k) {
-        const double a = (k < S::TPC - 1 || s < S::KR) ? areg[k][s] : atl[(w * S::KL + s - S::KR) * WAVE + lane];
+        const double a = tail_slot(k, s) < 0 ? areg[k][s] : atl[(w * S::NAT + tail_slot(k, s)) * WAVE + lane];
         acc[k] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bcur, acc[k], 0, 0, 0);
       }
       bcur = bnxt;
