@@ -245,7 +245,6 @@ struct AdjCrB {
   static constexpr int SPC = 4 * TPC;                         // slots per chunk
   static constexpr int NTRI = SPC % 3 == 0 ? SPC / 3 : (SPC + 4) / 3;  // node triples a chunk touches
   static_assert(NCH <= WPB, "one wave per output chunk");
-  // at Np = 120 the last tile's last KL k-steps' operands wait in LDS
   // A operands kept in LDS instead of registers: the last KL k-steps of the
   // chunk's last tile and the last KL2 of the one before it (at Np = 84 the
   // whole last tile and 3 more, which fills two workgroups' 160 KiB)
